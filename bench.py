@@ -1,0 +1,293 @@
+#!/usr/bin/env python3
+"""FPTC batch decompression benchmark on one MI355X.
+
+One step = the whole decode path over one batch already resident in HBM:
+plan (stream/chunk setup + symlen prefix sums) -> Huffman decode with
+compaction -> dequantization fused with the inverse DCT, float32 out.
+
+Default workload ("batch"): 4096 synthetic streams, lengths log-uniform in
+2^14..2^20 samples, domains EEG / seismic / power-grid / meteorological in
+turn, window 64, amplitude quantizer (steps 0.25 / 2.0, threshold 16), one
+codebook per domain trained on separate data, L_max 12.  "plain": one EEG-like
+stream of 2^20 samples with the same codec.
+
+Prints one JSON line: decoded GB/s (4 bytes per output sample / step time),
+the HBM roofline of the dominant kernel measured with HIP events, a
+per-stream-launch comparison and the CPU oracle timed on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+from concurrent.futures import ThreadPoolExecutor
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published peak
+STEP_F, STEP_C, THRESH = 0.25, 2.0, 16.0
+
+
+def host_threads() -> int:
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def make_workload(name: str, threads: int):
+    """Signals, stream lengths, per-stream domain and the codebook training data."""
+    import synth
+    if name == "batch":
+        config_id, n = 1, 4096
+        rng = np.random.default_rng(np.random.SeedSequence(synth.ROOT_SEED, spawn_key=(2, 1)))
+        lens = synth.batch_lengths(n, 14.0, 20.0, rng)
+        dom = np.arange(n) % 4
+    elif name == "plain":
+        config_id, n = 0, 1
+        lens = np.array([1 << 20], dtype=np.int64)
+        dom = np.zeros(1, dtype=np.int64)
+    else:
+        raise SystemExit(f"unknown workload {name}")
+    sample_off = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+    x = np.empty(int(sample_off[-1]), dtype=np.float32)
+
+    def gen(i):
+        x[sample_off[i]:sample_off[i + 1]] = synth.domain_signal(synth.DOMAINS[dom[i]], int(lens[i]),
+                                                                 synth.stream_rng(config_id, i))
+
+    order = np.argsort(-lens)  # longest first for balance
+    with ThreadPoolExecutor(threads) as ex:
+        list(ex.map(gen, order))
+    n_dom = 4 if name == "batch" else 1
+    train = [synth.domain_signal(synth.DOMAINS[d], 1 << 18, synth.training_rng(config_id, d)).astype(np.float32)
+             for d in range(n_dom)]
+    return x, sample_off, dom.astype(np.uint8), train
+
+
+def encode(x, sample_off, dom, train, q, threads):
+    from paper_2605_01086_amd import codec as C
+    from paper_2605_01086_amd import fptc as F
+    lens_tab = np.stack([C.train_code_lengths(t, q) for t in train])
+    L = np.diff(sample_off)
+    nsym = C.n_windows(L, q.N) * q.E
+    cap_off = np.concatenate([[0], np.cumsum(nsym + 1)]).astype(np.int64)
+    words = np.zeros(int(cap_off[-1]), dtype=np.uint64)
+    symlen = np.zeros(int(cap_off[-1]), dtype=np.uint8)
+    nw = F.fptc_encode_batch_host(x, sample_off, dom, q, lens_tab, cap_off, words, symlen, threads)
+    word_off = np.concatenate([[0], np.cumsum(nw)]).astype(np.int64)
+    # compact the per-stream reserved ranges
+    wc = np.empty(int(word_off[-1]), dtype=np.uint64)
+    sc = np.empty(int(word_off[-1]), dtype=np.uint8)
+    for i in range(len(nw)):
+        wc[word_off[i]:word_off[i + 1]] = words[cap_off[i]:cap_off[i] + nw[i]]
+        sc[word_off[i]:word_off[i + 1]] = symlen[cap_off[i]:cap_off[i] + nw[i]]
+    return wc, sc, word_off, lens_tab
+
+
+def time_batched(dec, steps, warmup, precision):
+    import torch
+    for _ in range(warmup):
+        dec.run(precision=precision)
+    torch.cuda.synchronize()
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(steps)]
+    t0 = time.perf_counter()
+    for k in range(steps):
+        e = ev[k]
+        e[0].record()
+        dec.plan()
+        e[1].record()
+        dec.decode()
+        e[2].record()
+        dec.dequant_idct(precision=precision)
+        e[3].record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    per = np.array([[e[i].elapsed_time(e[i + 1]) for i in range(3)] for e in ev])  # ms
+    gpu = np.array([e[0].elapsed_time(e[3]) for e in ev])
+    return wall / steps * 1e3, per.mean(axis=0), gpu
+
+
+def time_per_stream(batch, codec, launch, steps, precision):
+    """The same decode issued as one plan/decode/dequant+IDCT launch sequence per stream."""
+    import ctypes
+    import torch
+    from paper_2605_01086_amd import fptc as F
+    dev = batch.word_off.device
+    n = batch.n_streams
+    wo, so, yo = batch.word_off_h, batch.sample_off_h, batch.sym_off_h
+    loc_w = torch.from_numpy(np.stack([np.zeros(n, np.int64), np.diff(wo)], 1).copy()).to(dev)
+    loc_s = torch.from_numpy(np.stack([np.zeros(n, np.int64), np.diff(so)], 1).copy()).to(dev)
+    lib = F.load()
+    lc = launch.c()
+    structs = []
+    ws_bytes = 0
+    for s in range(n):
+        b = F.fptc_batch(1, 0, int(wo[s + 1] - wo[s]), int(yo[s + 1] - yo[s]), int(so[s + 1] - so[s]),
+                         batch.words.data_ptr() + 8 * int(wo[s]), batch.symlen.data_ptr() + int(wo[s]),
+                         loc_w.data_ptr() + 16 * s, loc_s.data_ptr() + 16 * s,
+                         None if batch.book_id is None else batch.book_id.data_ptr() + s)
+        structs.append(b)
+        ws_bytes = max(ws_bytes, F.fptc_workspace_size(b, codec.c, lc))
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
+    status = torch.zeros(n, dtype=torch.int32, device=dev)
+    sym = torch.empty(max(1, batch.n_symbols), dtype=torch.uint8, device=dev)
+    out = torch.empty(max(1, batch.n_samples), dtype=torch.float32, device=dev)
+    st = torch.cuda.current_stream().cuda_stream
+    by = ctypes.byref
+    cp = by(codec.c)
+    lp = by(lc)
+    prec = F.PRECISIONS[precision]
+
+    def one_pass():
+        for s in range(n):
+            bp = by(structs[s])
+            sp = status.data_ptr() + 4 * s
+            rc = lib.fptc_plan_batch(bp, cp, lp, ws.data_ptr(), ws_bytes, sp, st)
+            rc |= lib.fptc_decode_batch(bp, cp, lp, ws.data_ptr(), ws_bytes, sym.data_ptr() + int(yo[s]), sp, st)
+            rc |= lib.fptc_dequant_idct(bp, cp, lp, ws.data_ptr(), ws_bytes, sym.data_ptr() + int(yo[s]), None, prec,
+                                        out.data_ptr() + 4 * int(so[s]), st)
+            if rc:
+                raise RuntimeError("per-stream launch failed")
+
+    one_pass()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        one_pass()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / steps * 1e3
+    return ms, out
+
+
+def cpu_baseline(words, symlen, word_off, sample_off, dom, lens_tab, q, budget_s, threads):
+    """The CPU oracle (bit-serial decode + FP64 dequant/IDCT), timed on a bounded
+    sample of the same streams: streams in a fixed shuffled order until the
+    time budget is used."""
+    from oracle import oracle as O
+    p = O.QuantParams("amp", q.N, q.E, step_f=q.step_fine, step_c=q.step_coarse, T=q.threshold)
+    books = [O.Codebook(lens_tab[b]) for b in range(lens_tab.shape[0])]
+    n = len(sample_off) - 1
+    order = np.random.default_rng(7).permutation(n)
+    done = {"samples": 0, "streams": 0}
+    t0 = time.perf_counter()
+
+    def work(s):
+        if time.perf_counter() - t0 > budget_s:
+            return 0
+        L = int(sample_off[s + 1] - sample_off[s])
+        nsym = O.n_windows(L, q.N) * q.E
+        sym = O.symlen_decode(words[word_off[s]:word_off[s + 1]], symlen[word_off[s]:word_off[s + 1]],
+                              books[int(dom[s])], nsym)
+        O.reconstruct(sym, L, p)
+        return L
+
+    with ThreadPoolExecutor(threads) as ex:
+        res = list(ex.map(work, order))
+    dt = time.perf_counter() - t0
+    done["samples"] = int(sum(res))
+    done["streams"] = int(sum(1 for r in res if r))
+    return done, dt
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="batch", choices=["batch", "plain"])
+    ap.add_argument("--precision", default="fp32")
+    ap.add_argument("--wpc", type=int, default=32)
+    ap.add_argument("--waves", type=int, default=4)
+    ap.add_argument("--blocks", type=int, default=0)
+    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-per-stream", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only: the decode path has no multi-GPU split in this build "
+              f"(--gpus {args.gpus} requested)", file=sys.stderr)
+        sys.exit(2)
+
+    threads = host_threads()
+    t_setup = time.perf_counter()
+    from paper_2605_01086_amd import codec as C
+    q = C.quant_params("amp", 64, 64, step_fine=STEP_F, step_coarse=STEP_C, threshold=THRESH)
+    x, sample_off, dom, train = make_workload(args.workload, threads)
+    words, symlen, word_off, lens_tab = encode(x, sample_off, dom, train, q, threads)
+    n_samples = int(sample_off[-1])
+    del x
+    t_enc = time.perf_counter() - t_setup
+    print(f"[bench] workload {args.workload}: {len(sample_off) - 1} streams, {n_samples} samples, "
+          f"{len(words)} words, setup {t_enc:.1f}s", file=sys.stderr, flush=True)
+
+    import torch
+    torch.cuda.set_device(0)
+    codec = C.DeviceCodec(lens_tab, q, 12)
+    batch = C.DeviceBatch(words, symlen, word_off, sample_off, q.N, q.E, dom if args.workload == "batch" else None)
+    launch = C.Launch(args.wpc, args.waves, args.blocks)
+    dec = C.Decoder(batch, codec, launch)
+    ms_step, per_kernel, gpu_steps = time_batched(dec, args.steps, args.warmup, args.precision)
+    status = dec.status.cpu().numpy()
+    if np.any(status != 0):
+        raise SystemExit(f"decode reported stream errors: {np.flatnonzero(status)[:8]}")
+
+    out_bytes = 4 * n_samples
+    value = out_bytes / (ms_step * 1e-3) / 1e9
+    comp_bytes = batch.compressed_bytes + batch.header_bytes
+    # algorithmic bytes per launch of each kernel (measurement)
+    alg = {"plan": batch.n_words + batch.header_bytes,
+           "decode": batch.compressed_bytes + batch.header_bytes + batch.n_symbols,
+           "dequant_idct": batch.n_symbols + out_bytes}
+    names = ["plan", "decode", "dequant_idct"]
+    dom_k = int(np.argmax(per_kernel))
+    kname = names[dom_k]
+    achieved = alg[kname] / (per_kernel[dom_k] * 1e-3) / 1e9
+    roof = {"bound": "hbm", "kernel": {"decode": "k_decode", "dequant_idct": "k_dqidct_f32",
+                                       "plan": "k_plan_chunks"}[kname],
+            "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None}
+    path_alg = comp_bytes + out_bytes
+    path_roofline_decoded = HBM_PEAK_GBS * out_bytes / path_alg
+    line = {
+        "metric": "decoded GB/s (float32 output) + % HBM roofline, batched vs plain, at 1 MI355X",
+        "value": round(value, 2), "unit": "GB/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"fptc-{args.workload}", "streams": int(len(sample_off) - 1),
+                   "samples": n_samples, "window": q.N, "kept_coeffs": q.E, "quantizer": "amplitude 0.25/2.0/T16",
+                   "lmax": 12, "precision": args.precision, "windows_per_chunk": args.wpc,
+                   "waves_per_block": args.waves, "compressed_bytes": int(comp_bytes),
+                   "bytes_per_sample_in": round(comp_bytes / n_samples, 4)},
+        "roofline": roof,
+        "path_roofline": {"algorithmic_bytes": int(path_alg), "achieved_GBs": round(path_alg / (ms_step * 1e-3) / 1e9, 1),
+                          "frac": round(path_alg / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                          "roofline_decoded_GBs": round(path_roofline_decoded, 1),
+                          "decoded_frac_of_roofline": round(value / path_roofline_decoded, 4)},
+        "kernel_ms": {k: round(float(v), 4) for k, v in zip(names, per_kernel)},
+        "gpu_ms_per_step": {"median": round(float(np.median(gpu_steps)), 4), "min": round(float(gpu_steps.min()), 4),
+                            "max": round(float(gpu_steps.max()), 4)},
+    }
+    if not args.no_per_stream and args.workload == "batch":
+        ms_ps, out_ps = time_per_stream(batch, codec, launch, 3, args.precision)
+        same = bool(torch.equal(out_ps[:n_samples], dec.out[:n_samples]))
+        line["per_stream_launches"] = {"value": round(out_bytes / (ms_ps * 1e-3) / 1e9, 2), "unit": "GB/s",
+                                       "ms_per_step": round(ms_ps, 3), "launches_per_step": 4 * batch.n_streams,
+                                       "bitwise_equal_to_batched": same}
+    if not args.no_cpu_baseline:
+        done, dt = cpu_baseline(words, symlen, word_off, sample_off, dom, lens_tab, q, args.cpu_budget, threads)
+        line["cpu_baseline"] = {"value": round(4 * done["samples"] / dt / 1e9, 5), "unit": "GB/s", "cores": threads,
+                                "kind": "oracle",
+                                "sample": f"{done['streams']} of {len(sample_off) - 1} streams "
+                                          f"({done['samples']} samples) in {dt:.1f}s, fixed shuffled order"}
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

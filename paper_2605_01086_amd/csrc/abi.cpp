@@ -1,0 +1,154 @@
+// C ABI entry points of the device path: argument checks on the host, the
+// workspace layout, and the launches.  Every check runs before anything is
+// enqueued, so an error return leaves the stream untouched.
+#include <hip/hip_runtime.h>
+
+#include <mutex>
+#include <vector>
+
+#include "fptc_internal.h"
+
+namespace fptc {
+
+namespace {
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+bool valid_n(int32_t N) {
+  return N == 4 || N == 8 || N == 16 || N == 32 || N == 64 || N == 128 || N == 256;
+}
+
+int check_batch(const fptc_batch *b) {
+  if (!b || b->n_streams < 1 || b->n_words < 0 || b->n_symbols < 0 || b->n_samples < 0) return FPTC_ERR_INVALID_ARG;
+  if (!b->word_off || !b->sample_off) return FPTC_ERR_INVALID_ARG;
+  if (b->n_words > 0 && (!b->words || !b->symlen)) return FPTC_ERR_INVALID_ARG;
+  return FPTC_OK;
+}
+
+int check_codec(const fptc_codec *c) {
+  if (!c || !valid_n(c->N) || c->E < 1 || c->E > c->N) return FPTC_ERR_INVALID_ARG;
+  if (c->lmax < 1 || c->lmax > kMaxLmax || c->n_books < 1 || c->n_books > kMaxBooks) return FPTC_ERR_INVALID_ARG;
+  if (c->n_rows < 1 || c->n_rows > kMaxRows) return FPTC_ERR_INVALID_ARG;
+  if (!c->lut || !c->deq_val || !c->deq_zone || !c->row_of_bin || !c->basis) return FPTC_ERR_INVALID_ARG;
+  return FPTC_OK;
+}
+
+int resolve_shape(const fptc_launch *l, const fptc_codec *c, Shape *s) {
+  s->wpc = (l && l->windows_per_chunk) ? l->windows_per_chunk : kDefaultWindowsPerChunk;
+  s->waves = (l && l->waves_per_block) ? l->waves_per_block : kDefaultWavesPerBlock;
+  s->blocks = l ? l->blocks : 0;
+  if (s->wpc < 1 || s->wpc > 1024 || s->waves < 1 || s->waves > 16 || s->blocks < 0) return FPTC_ERR_INVALID_ARG;
+  // LDS budget of the decode kernel: lookup tables + one symbol buffer per wave.
+  size_t lut = ((size_t)(c->n_books << c->lmax) * 2 + 15) & ~(size_t)15;
+  size_t buf = (((size_t)s->wpc * c->E + 16) + 15) & ~(size_t)15;
+  if (lut + s->waves * buf > 64 * 1024) return FPTC_ERR_UNSUPPORTED;
+  return FPTC_OK;
+}
+
+int status_of(int hip_err) { return hip_err == 0 ? FPTC_OK : FPTC_ERR_HIP; }
+
+}  // namespace
+
+Layout layout_for(const fptc_batch *b, const fptc_codec *c, const Shape &s) {
+  Layout L{};
+  const int64_t n = b->n_streams;
+  const int64_t max_windows = b->n_symbols / c->E;
+  L.chunk_cap = (max_windows + s.wpc - 1) / s.wpc + n + 1;
+  size_t off = 0;
+  L.hdr = off;
+  off = align256(off + 8 * sizeof(int64_t));
+  L.win_off = off;
+  off = align256(off + (n + 1) * sizeof(int64_t));
+  L.chunk_off = off;
+  off = align256(off + (n + 1) * sizeof(int64_t));
+  L.chunk_word = off;
+  off = align256(off + L.chunk_cap * sizeof(int64_t));
+  L.chunk_wsym = off;
+  off = align256(off + L.chunk_cap * sizeof(int64_t));
+  L.bwd_part = off;
+  off = align256(off + L.chunk_cap * 3 * sizeof(double));
+  L.total = off;
+  return L;
+}
+
+Plan plan_view(void *ws, const Layout &L) {
+  char *p = static_cast<char *>(ws);
+  Plan v;
+  v.hdr = reinterpret_cast<int64_t *>(p + L.hdr);
+  v.win_off = reinterpret_cast<int64_t *>(p + L.win_off);
+  v.chunk_off = reinterpret_cast<int64_t *>(p + L.chunk_off);
+  v.chunk_word = reinterpret_cast<int64_t *>(p + L.chunk_word);
+  v.chunk_wsym = reinterpret_cast<int64_t *>(p + L.chunk_wsym);
+  v.bwd_part = reinterpret_cast<double *>(p + L.bwd_part);
+  v.chunk_cap = L.chunk_cap;
+  return v;
+}
+
+int device_cu_count() {
+  // Cached per device; guarded because several host threads may launch.
+  static std::mutex mu;
+  static std::vector<int> cache;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 256;
+  std::lock_guard<std::mutex> g(mu);
+  if ((int)cache.size() <= dev) cache.resize(dev + 1, 0);
+  if (!cache[dev]) {
+    int cu = 0;
+    if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cu <= 0) cu = 256;
+    cache[dev] = cu;
+  }
+  return cache[dev];
+}
+
+}  // namespace fptc
+
+using namespace fptc;
+
+extern "C" {
+
+size_t fptc_workspace_size(const fptc_batch *batch, const fptc_codec *codec, const fptc_launch *launch) {
+  Shape s;
+  if (check_batch(batch) || check_codec(codec) || resolve_shape(launch, codec, &s)) return 0;
+  return layout_for(batch, codec, s).total;
+}
+
+int32_t fptc_plan_batch(const fptc_batch *batch, const fptc_codec *codec, const fptc_launch *launch, void *ws,
+                        size_t ws_bytes, int32_t *stream_status, void *stream) {
+  Shape s;
+  int rc;
+  if ((rc = check_batch(batch)) || (rc = check_codec(codec)) || (rc = resolve_shape(launch, codec, &s))) return rc;
+  if (!ws) return FPTC_ERR_INVALID_ARG;
+  Layout L = layout_for(batch, codec, s);
+  if (ws_bytes < L.total) return FPTC_ERR_WORKSPACE;
+  return status_of(launch_plan(*batch, *codec, s, plan_view(ws, L), stream_status, stream));
+}
+
+int32_t fptc_decode_batch(const fptc_batch *batch, const fptc_codec *codec, const fptc_launch *launch,
+                          const void *ws, size_t ws_bytes, uint8_t *symbols_out, int32_t *stream_status,
+                          void *stream) {
+  Shape s;
+  int rc;
+  if ((rc = check_batch(batch)) || (rc = check_codec(codec)) || (rc = resolve_shape(launch, codec, &s))) return rc;
+  if (!ws || (!symbols_out && batch->n_symbols > 0)) return FPTC_ERR_INVALID_ARG;
+  Layout L = layout_for(batch, codec, s);
+  if (ws_bytes < L.total) return FPTC_ERR_WORKSPACE;
+  return status_of(
+      launch_decode(*batch, *codec, s, plan_view(const_cast<void *>(ws), L), symbols_out, stream_status, stream));
+}
+
+int32_t fptc_dequant_idct(const fptc_batch *batch, const fptc_codec *codec, const fptc_launch *launch,
+                          const void *ws, size_t ws_bytes, const uint8_t *symbols, const float *gamma,
+                          int32_t precision, float *out, void *stream) {
+  Shape s;
+  int rc;
+  if ((rc = check_batch(batch)) || (rc = check_codec(codec)) || (rc = resolve_shape(launch, codec, &s))) return rc;
+  if (!ws || (!symbols && batch->n_symbols > 0) || (!out && batch->n_samples > 0)) return FPTC_ERR_INVALID_ARG;
+  if (precision < FPTC_FP32_SIMT || precision > FPTC_BF16X3) return FPTC_ERR_INVALID_ARG;
+  if (precision != FPTC_FP32_SIMT) return FPTC_ERR_UNSUPPORTED;
+  Layout L = layout_for(batch, codec, s);
+  if (ws_bytes < L.total) return FPTC_ERR_WORKSPACE;
+  return status_of(launch_dqidct(*batch, *codec, s, plan_view(const_cast<void *>(ws), L), symbols, gamma, precision,
+                                 out, stream));
+}
+
+}  // extern "C"

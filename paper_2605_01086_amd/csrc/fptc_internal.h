@@ -1,0 +1,63 @@
+// Internal declarations shared by the library's translation units: the
+// workspace layout of a plan and the kernel launchers.  Not part of the ABI.
+#pragma once
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/fptc.h"
+
+namespace fptc {
+
+constexpr int kWave = 64;
+constexpr int kDefaultWindowsPerChunk = 32;
+constexpr int kDefaultWavesPerBlock = 4;
+constexpr int kMaxBooks = 8;
+constexpr int kMaxRows = 4;
+constexpr int kMaxLmax = 12;
+
+// Resolved launch shape (defaults applied, validated).
+struct Shape {
+  int wpc;     // windows per chunk
+  int waves;   // waves per block
+  int blocks;  // persistent grid size (0 = launcher decides)
+};
+
+// Workspace layout of a plan.  Every section starts on a 256-byte boundary.
+//   hdr        int64[8]     [0] = chunk count, [1] = window count
+//   win_off    int64[n+1]   exclusive prefix of ceil(L_s / N)
+//   chunk_off  int64[n+1]   exclusive prefix of ceil(n_win_s / wpc) (0 for bad headers)
+//   chunk_word int64[cap]   global index of the first word holding a symbol of the chunk, -1 if none
+//   chunk_wsym int64[cap]   in-stream index of that word's first symbol
+//   bwd_part   double[cap*3] backward partial sums per chunk and zone
+struct Layout {
+  size_t hdr, win_off, chunk_off, chunk_word, chunk_wsym, bwd_part, total;
+  int64_t chunk_cap;
+};
+
+Layout layout_for(const fptc_batch *b, const fptc_codec *c, const Shape &s);
+
+// Pointers into a workspace.
+struct Plan {
+  int64_t *hdr;
+  int64_t *win_off;
+  int64_t *chunk_off;
+  int64_t *chunk_word;
+  int64_t *chunk_wsym;
+  double *bwd_part;
+  int64_t chunk_cap;
+};
+
+Plan plan_view(void *ws, const Layout &L);
+
+// Kernel launchers (return hipError_t as int).
+int launch_plan(const fptc_batch &b, const fptc_codec &c, const Shape &s, const Plan &p, int32_t *status,
+                void *stream);
+int launch_decode(const fptc_batch &b, const fptc_codec &c, const Shape &s, const Plan &p, uint8_t *symbols,
+                  int32_t *status, void *stream);
+int launch_dqidct(const fptc_batch &b, const fptc_codec &c, const Shape &s, const Plan &p,
+                  const uint8_t *symbols, const float *gamma, int precision, float *out, void *stream);
+
+int device_cu_count();
+
+}  // namespace fptc

@@ -1,0 +1,160 @@
+// Batch planning kernels (stream/chunk setup and the symlen prefix sums).
+//
+// Section 4.2 places each word's decoded symbols by an exclusive prefix sum of
+// the per-word symbol counts.  Here the sum is taken per stream, and only the
+// words where a chunk of `wpc` windows begins are recorded: a chunk then
+// decodes from that word on its own, with no cross-chunk dependency.
+#include <hip/hip_runtime.h>
+
+#include "fptc_internal.h"
+
+namespace fptc {
+namespace {
+
+constexpr int kPlanThreads = 1024;
+constexpr int kScanThreads = 256;
+constexpr int kWordsPerThread = 4;
+
+// Inclusive scan across one 64-lane wavefront.
+template <typename T>
+__device__ inline T wave_incl_scan(T v) {
+  const int lane = threadIdx.x & (kWave - 1);
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    T u = __shfl_up(v, d, kWave);
+    if (lane >= d) v += u;
+  }
+  return v;
+}
+
+// Exclusive block scan; returns the exclusive prefix of v and the block total.
+template <typename T, int THREADS>
+__device__ inline T block_excl_scan(T v, T *lds, T &total) {
+  const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+  constexpr int NW = THREADS / kWave;
+  T incl = wave_incl_scan(v);
+  if (lane == kWave - 1) lds[wid] = incl;
+  __syncthreads();
+  if (wid == 0) {
+    T x = lane < NW ? lds[lane] : T(0);
+    T xi = wave_incl_scan(x);
+    if (lane < NW) lds[lane] = xi - x;
+    if (lane == NW - 1) lds[NW] = xi;
+  }
+  __syncthreads();
+  T r = incl - v + lds[wid];
+  total = lds[NW];
+  __syncthreads();
+  return r;
+}
+
+// One workgroup: per-stream window counts and chunk counts, their exclusive
+// prefix sums, and header validation.
+__global__ void __launch_bounds__(kPlanThreads) k_plan_streams(fptc_batch b, int N, int E, int wpc,
+                                                               int64_t *hdr, int64_t *win_off, int64_t *chunk_off,
+                                                               int32_t *status) {
+  __shared__ int64_t lds[kPlanThreads / kWave + 1];
+  const int n = b.n_streams;
+  const int64_t win_cap = b.n_symbols / E;
+  int64_t carry_w = 0, carry_c = 0;
+  for (int base = 0; base < n; base += kPlanThreads) {
+    const int s = base + threadIdx.x;
+    int64_t nw = 0;
+    int flag = 0;
+    if (s < n) {
+      const int64_t s0 = b.sample_off[s], s1 = b.sample_off[s + 1];
+      const int64_t w0 = b.word_off[s], w1 = b.word_off[s + 1];
+      if (s0 < 0 || s1 < s0 || s1 > b.n_samples || w0 < 0 || w1 < w0 || w1 > b.n_words) flag = FPTC_STREAM_BAD_HEADER;
+      else nw = (s1 - s0 + N - 1) / N;
+    }
+    int64_t tot;
+    const int64_t wo = carry_w + block_excl_scan<int64_t, kPlanThreads>(nw, lds, tot);
+    carry_w += tot;
+    if (s < n && !flag && (wo + nw) > win_cap) flag = FPTC_STREAM_BAD_HEADER;
+    const int64_t nc = flag ? 0 : (nw + wpc - 1) / wpc;
+    const int64_t co = carry_c + block_excl_scan<int64_t, kPlanThreads>(nc, lds, tot);
+    carry_c += tot;
+    if (s < n) {
+      win_off[s] = wo;
+      chunk_off[s] = co;
+      if (status) status[s] = flag;
+    }
+  }
+  if (threadIdx.x == 0) {
+    win_off[n] = carry_w;
+    chunk_off[n] = carry_c;
+    hdr[0] = carry_c;
+    hdr[1] = carry_w < win_cap ? carry_w : win_cap;
+  }
+}
+
+// One workgroup per stream: exclusive scan of the stream's symlen; every word
+// whose symbol range [p, p + symlen) contains the first symbol of a chunk
+// (a multiple of wpc * E) is recorded as that chunk's first word.  Also checks
+// the symbol total and the symlen bound.
+__global__ void __launch_bounds__(kScanThreads) k_plan_chunks(fptc_batch b, int N, int E, int wpc,
+                                                              const int64_t *win_off, const int64_t *chunk_off,
+                                                              int64_t *chunk_word, int64_t *chunk_wsym,
+                                                              int32_t *status) {
+  __shared__ int64_t lds[kScanThreads / kWave + 1];
+  const int s = blockIdx.x;
+  const int64_t c0 = chunk_off[s], nc = chunk_off[s + 1] - c0;
+  if (nc <= 0) return;  // empty stream or bad header (then status already flagged)
+  for (int64_t i = threadIdx.x; i < nc; i += kScanThreads) chunk_word[c0 + i] = -1;
+  __syncthreads();
+  const int64_t w0 = b.word_off[s], w1 = b.word_off[s + 1];
+  const int64_t nw = win_off[s + 1] - win_off[s];
+  const int64_t cb = (int64_t)wpc * E;  // symbols per chunk
+  int64_t carry = 0;
+  int bad = 0;
+  for (int64_t base = w0; base < w1; base += (int64_t)kScanThreads * kWordsPerThread) {
+    const int64_t wb = base + (int64_t)threadIdx.x * kWordsPerThread;
+    int cnt[kWordsPerThread];
+    int sum = 0;
+#pragma unroll
+    for (int j = 0; j < kWordsPerThread; ++j) {
+      const int64_t w = wb + j;
+      int c = w < w1 ? (int)b.symlen[w] : 0;
+      if (c > 64) {
+        bad |= FPTC_STREAM_BAD_SYMLEN;
+        c = 64;
+      }
+      cnt[j] = c;
+      sum += c;
+    }
+    int64_t tot;
+    int64_t p = carry + block_excl_scan<int64_t, kScanThreads>((int64_t)sum, lds, tot);
+    carry += tot;
+#pragma unroll
+    for (int j = 0; j < kWordsPerThread; ++j) {
+      const int c = cnt[j];
+      if (c > 0) {
+        // chunk starts m * cb with p <= m * cb < p + c
+        int64_t m = (p + cb - 1) / cb;
+        for (; m * cb < p + c && m < nc; ++m) {
+          chunk_word[c0 + m] = wb + j;
+          chunk_wsym[c0 + m] = p;
+        }
+      }
+      p += c;
+    }
+  }
+  if (threadIdx.x == 0 && carry != nw * E) bad |= FPTC_STREAM_BAD_COUNT;
+  if (bad && status) atomicOr(&status[s], bad);
+}
+
+}  // namespace
+
+int launch_plan(const fptc_batch &b, const fptc_codec &c, const Shape &s, const Plan &p, int32_t *status,
+                void *stream) {
+  hipStream_t st = (hipStream_t)stream;
+  hipLaunchKernelGGL(k_plan_streams, dim3(1), dim3(kPlanThreads), 0, st, b, c.N, c.E, s.wpc, p.hdr, p.win_off,
+                     p.chunk_off, status);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return (int)e;
+  hipLaunchKernelGGL(k_plan_chunks, dim3(b.n_streams), dim3(kScanThreads), 0, st, b, c.N, c.E, s.wpc, p.win_off,
+                     p.chunk_off, p.chunk_word, p.chunk_wsym, status);
+  return (int)hipGetLastError();
+}
+
+}  // namespace fptc

@@ -7,6 +7,7 @@ evaluated on (biomedical, seismic, power-grid, meteorological).
 """
 from .signals import (  # noqa: F401
     DOMAINS,
+    ROOT_SEED,
     eeg_like,
     seismic_like,
     power_like,
