@@ -17,6 +17,15 @@ import torch
 from . import fptc as F
 
 
+def to_device(a: np.ndarray, dev) -> torch.Tensor:
+    """C-contiguous device copy of a host array.  The C ABI takes raw pointers
+    to dense row-major buffers, so any other layout is refused here."""
+    t = torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    if not t.is_contiguous():
+        raise ValueError("device buffers passed to libfptc must be contiguous")
+    return t
+
+
 def quant_params(kind: str = "amp", N: int = 64, E: int | None = None, step_fine: float = 0.25,
                  step_coarse: float = 2.0, threshold: float = 16.0, B1: int = 2, B2: int = 16, mu: float = 50.0,
                  alpha1: float = 0.004, A0: float = 1.0, A1: float = 1.0) -> F.fptc_quant_params:
@@ -36,17 +45,17 @@ class DeviceCodec:
         val, zone, rob = F.fptc_build_dequant(q)
         self.n_rows = val.shape[0]
         # every book shares the quantizer; each has its own table copy so books may differ
-        vals = np.array(np.broadcast_to(val, (self.n_books,) + val.shape))
-        zones = np.array(np.broadcast_to(zone, (self.n_books,) + zone.shape))
-        robs = np.array(np.broadcast_to(rob, (self.n_books,) + rob.shape))
+        vals = np.tile(val, (self.n_books, 1, 1))
+        zones = np.tile(zone, (self.n_books, 1, 1))
+        robs = np.tile(rob, (self.n_books, 1))
         basis = F.fptc_build_basis(q.N, q.E)
         dev = torch.device(device)
         self.host = dict(lut=luts, deq_val=vals, deq_zone=zones, row_of_bin=robs, basis=basis, code_lens=code_lens)
-        self.lut = torch.from_numpy(luts.view(np.int16)).to(dev)
-        self.deq_val = torch.from_numpy(vals).to(dev)
-        self.deq_zone = torch.from_numpy(zones).to(dev)
-        self.row_of_bin = torch.from_numpy(robs).to(dev)
-        self.basis = torch.from_numpy(basis).to(dev)
+        self.lut = to_device(luts.view(np.int16), dev)
+        self.deq_val = to_device(vals, dev)
+        self.deq_zone = to_device(zones, dev)
+        self.row_of_bin = to_device(robs, dev)
+        self.basis = to_device(basis, dev)
         self.c = F.fptc_codec(self.N, self.E, lmax, self.n_books, self.n_rows, 0, self.lut.data_ptr(),
                               self.deq_val.data_ptr(), self.deq_zone.data_ptr(), self.row_of_bin.data_ptr(),
                               self.basis.data_ptr())
@@ -71,15 +80,14 @@ class DeviceBatch:
         self.n_symbols = int(self.sym_off_h[-1])
         self.n_samples = int(self.sample_off_h[-1])
         w = np.ascontiguousarray(words, dtype=np.uint64)
-        self.words = torch.from_numpy(w.view(np.int64)).to(dev) if w.size else torch.zeros(1, dtype=torch.int64,
-                                                                                             device=dev)
+        self.words = to_device(w.view(np.int64), dev) if w.size else torch.zeros(1, dtype=torch.int64, device=dev)
         sl = np.ascontiguousarray(symlen, dtype=np.uint8)
-        self.symlen = torch.from_numpy(sl).to(dev) if sl.size else torch.zeros(1, dtype=torch.uint8, device=dev)
-        self.word_off = torch.from_numpy(self.word_off_h).to(dev)
-        self.sample_off = torch.from_numpy(self.sample_off_h).to(dev)
+        self.symlen = to_device(sl, dev) if sl.size else torch.zeros(1, dtype=torch.uint8, device=dev)
+        self.word_off = to_device(self.word_off_h, dev)
+        self.sample_off = to_device(self.sample_off_h, dev)
         self.book_id = None
         if book_id is not None:
-            self.book_id = torch.from_numpy(np.ascontiguousarray(book_id, dtype=np.uint8)).to(dev)
+            self.book_id = to_device(np.ascontiguousarray(book_id, dtype=np.uint8), dev)
         self.c = F.fptc_batch(self.n_streams, 0, self.n_words, self.n_symbols, self.n_samples,
                               self.words.data_ptr(), self.symlen.data_ptr(), self.word_off.data_ptr(),
                               self.sample_off.data_ptr(), None if self.book_id is None else self.book_id.data_ptr())

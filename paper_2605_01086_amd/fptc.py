@@ -116,7 +116,11 @@ def _ptr(t):
     if t is None:
         return None
     if isinstance(t, np.ndarray):
+        if not t.flags["C_CONTIGUOUS"]:
+            raise ValueError("host arrays passed to libfptc must be C-contiguous")
         return t.ctypes.data
+    if not t.is_contiguous():
+        raise ValueError("tensors passed to libfptc must be contiguous")
     return t.data_ptr()
 
 

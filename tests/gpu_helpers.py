@@ -54,6 +54,33 @@ def run_gpu(case: Case, launch=None, precision="fp32", use_gamma=True, words_ove
     return dict(sym=s_h[:batch.n_symbols], out=o_h[:batch.n_samples], status=st_h, batch=batch, runs=results)
 
 
+def _diagnose(case: Case, res, bad_stream: int) -> str:
+    """Describe which windows of which streams disagree; dump arrays for offline study."""
+    import os
+    batch = res["batch"]
+    N = case.p.N
+    lines = []
+    nbad_streams = 0
+    for i in range(len(case.signals)):
+        o0, o1 = batch.sample_off_h[i], batch.sample_off_h[i + 1]
+        d = np.abs(res["out"][o0:o1].astype(np.float64) - case.recon[i])
+        rng = float(np.ptp(case.recon[i])) if case.recon[i].size else 1.0
+        bad = np.flatnonzero(d > 1e-5 * max(rng, 1e-30))
+        if bad.size:
+            nbad_streams += 1
+            wins = np.unique(bad // N)
+            if len(lines) < 6:
+                lines.append(f"stream {i}: L={o1 - o0} bad samples {bad.size} in {wins.size} windows "
+                             f"(first {wins[:6].tolist()}), got {res['out'][o0 + bad[0]]:.4f} "
+                             f"want {case.recon[i][bad[0]]:.4f}")
+    lines.insert(0, f"{nbad_streams} of {len(case.signals)} streams disagree")
+    if os.path.isdir("gpurun_out"):
+        np.savez_compressed(f"gpurun_out/parity_fail_stream{bad_stream}.npz", out=res["out"], sym=res["sym"],
+                            recon=np.concatenate(case.recon) if case.recon else np.zeros(0),
+                            sample_off=batch.sample_off_h, sym_off=batch.sym_off_h)
+    return "\n".join(lines)
+
+
 def check_parity(case: Case, res, tol=1e-5, skip=()):
     batch = res["batch"]
     worst = 0.0
@@ -67,5 +94,6 @@ def check_parity(case: Case, res, tol=1e-5, skip=()):
         o0, o1 = batch.sample_off_h[i], batch.sample_off_h[i + 1]
         err = range_rel_err(res["out"][o0:o1], case.recon[i])
         worst = max(worst, err)
-        assert err <= tol, f"stream {i}: range-relative error {err:.3e} > {tol}"
+        if err > tol:
+            raise AssertionError(f"stream {i}: range-relative error {err:.3e} > {tol}\n" + _diagnose(case, res, i))
     return worst

@@ -162,3 +162,21 @@ def test_argument_errors_return_before_any_launch():
     bb, cc, ll = _fake_structs()
     cc.N, cc.E, ll.windows_per_chunk = 256, 256, 1024
     assert F.fptc_workspace_size(bb, cc, ll) == 0
+
+
+def test_codec_tables_are_dense_row_major_per_book(O):
+    # regression: per-book table copies must reach the C ABI as dense
+    # [n_books][n_rows][256] buffers whatever numpy layout they were built in
+    from paper_2605_01086_amd import codec as C
+    lens = np.stack([_trained_lengths(O, d) for d in ("eeg", "seismic", "power")])
+    q = C.quant_params("paper", 32, 16, B1=2, B2=10, mu=50.0, alpha1=0.004, A0=41.5, A1=7.25)
+    cd = C.DeviceCodec(lens, q, 12, device="cpu")
+    val, zone, rob = F.fptc_build_dequant(q)
+    for t in (cd.lut, cd.deq_val, cd.deq_zone, cd.row_of_bin, cd.basis):
+        assert t.is_contiguous()
+    flat = cd.deq_val.numpy().ravel()
+    for b in range(3):
+        assert np.array_equal(flat[b * 3 * 256:(b + 1) * 3 * 256], val.ravel())
+        assert np.array_equal(cd.lut.numpy().view(np.uint16)[b], F.fptc_build_lut(lens[b], 12))
+    with pytest.raises(ValueError):
+        F._ptr(np.zeros((4, 4))[:, ::2])
