@@ -67,6 +67,9 @@ Layout layout_for(const fptc_batch *b, const fptc_codec *c, const Shape &s) {
   off = align256(off + L.chunk_cap * sizeof(int64_t));
   L.bwd_part = off;
   off = align256(off + L.chunk_cap * 3 * sizeof(double));
+  L.tile_cap = (max_windows + kTileWindows - 1) / kTileWindows + 1;
+  L.tile_stream = off;
+  off = align256(off + L.tile_cap * sizeof(int32_t));
   L.total = off;
   return L;
 }
@@ -80,7 +83,9 @@ Plan plan_view(void *ws, const Layout &L) {
   v.chunk_word = reinterpret_cast<int64_t *>(p + L.chunk_word);
   v.chunk_wsym = reinterpret_cast<int64_t *>(p + L.chunk_wsym);
   v.bwd_part = reinterpret_cast<double *>(p + L.bwd_part);
+  v.tile_stream = reinterpret_cast<int32_t *>(p + L.tile_stream);
   v.chunk_cap = L.chunk_cap;
+  v.tile_cap = L.tile_cap;
   return v;
 }
 
@@ -144,11 +149,13 @@ int32_t fptc_dequant_idct(const fptc_batch *batch, const fptc_codec *codec, cons
   if ((rc = check_batch(batch)) || (rc = check_codec(codec)) || (rc = resolve_shape(launch, codec, &s))) return rc;
   if (!ws || (!symbols && batch->n_symbols > 0) || (!out && batch->n_samples > 0)) return FPTC_ERR_INVALID_ARG;
   if (precision < FPTC_FP32_SIMT || precision > FPTC_BF16X3) return FPTC_ERR_INVALID_ARG;
-  if (precision != FPTC_FP32_SIMT) return FPTC_ERR_UNSUPPORTED;
+  if (precision != FPTC_FP32_SIMT && !mfma_supported(codec->N, codec->E, precision)) return FPTC_ERR_UNSUPPORTED;
   Layout L = layout_for(batch, codec, s);
   if (ws_bytes < L.total) return FPTC_ERR_WORKSPACE;
-  return status_of(launch_dqidct(*batch, *codec, s, plan_view(const_cast<void *>(ws), L), symbols, gamma, precision,
-                                 out, stream));
+  Plan pv = plan_view(const_cast<void *>(ws), L);
+  if (precision == FPTC_FP32_SIMT)
+    return status_of(launch_dqidct(*batch, *codec, s, pv, symbols, gamma, precision, out, stream));
+  return status_of(launch_dqidct_mfma(*batch, *codec, s, pv, symbols, gamma, precision, out, stream));
 }
 
 }  // extern "C"

@@ -1,0 +1,369 @@
+// Dequantization fused with the inverse DCT on the matrix cores (Section 4.2,
+// lossy stage, as a dense contraction).
+//
+// For a tile of 32 consecutive windows (global numbering) one wavefront forms
+//     D[n][w] = sum_k B[k][n] * c[w][k]
+// i.e. the transposed product basis^T x coefficients^T, with
+// v_mfma_f32_32x32x16_{f16,bf16}: FP32 accumulation, 16-bit operands.  The
+// transposed form leaves each lane holding four consecutive samples of one
+// window, so the result leaves as 16-byte stores.
+//
+// Bins are mapped to MFMA k-slots so that each lane's coefficients are one
+// contiguous run of symbols: lane half h owns bins [h*Kp/2, (h+1)*Kp/2), k-step
+// s covers the 8 bins h*Kp/2 + 8 s + j.  The basis operand uses the same map.
+//
+// FP32-level accuracy comes from splitting operands into 16-bit pieces:
+//   FP16X2: basis = hi + lo (scaled by 2^10 so lo stays out of the FP16
+//           subnormal range); a coefficient that is not exact in FP16 (any
+//           per-zone scale != 1) is split too, and the pass with its lo piece
+//           is skipped when every lane's lo piece is zero.
+//   BF16X3: basis = hi + mid + lo in BF16, coefficients likewise.
+// The basis pieces live in LDS (rows padded by 16 bytes to spread banks); the
+// dequantization tables live in LDS; coefficients are dequantized in registers
+// straight from the decoded symbols.
+#include <hip/hip_runtime.h>
+
+#include "fptc_internal.h"
+
+namespace fptc {
+namespace {
+
+typedef _Float16 h8 __attribute__((ext_vector_type(8)));
+typedef __bf16 b8 __attribute__((ext_vector_type(8)));
+typedef uint16_t u8v __attribute__((ext_vector_type(8)));  // 8 raw 16-bit operand values
+typedef float f16v __attribute__((ext_vector_type(16)));
+
+constexpr int kThreads = 256;
+constexpr float kBasisScaleF16 = 1024.0f;  // 2^10, undone exactly on the output
+
+template <int PREC>
+struct Traits;
+template <>
+struct Traits<FPTC_FP16> {
+  static constexpr int kBPieces = 1, kAPieces = 1;
+  static constexpr bool kF16 = true;
+};
+template <>
+struct Traits<FPTC_FP16X2> {
+  static constexpr int kBPieces = 2, kAPieces = 2;
+  static constexpr bool kF16 = true;
+};
+template <>
+struct Traits<FPTC_BF16> {
+  static constexpr int kBPieces = 1, kAPieces = 1;
+  static constexpr bool kF16 = false;
+};
+template <>
+struct Traits<FPTC_BF16X3> {
+  static constexpr int kBPieces = 3, kAPieces = 3;
+  static constexpr bool kF16 = false;
+};
+
+// Split x into up to P 16-bit pieces whose sum approximates x.
+template <bool F16, int P>
+__device__ inline void split(float x, uint16_t *out) {
+  float r = x;
+#pragma unroll
+  for (int i = 0; i < P; ++i) {
+    if constexpr (F16) {
+      _Float16 h = (_Float16)r;
+      out[i] = __builtin_bit_cast(uint16_t, h);
+      r -= (float)h;
+    } else {
+      __bf16 h = (__bf16)r;
+      out[i] = __builtin_bit_cast(uint16_t, h);
+      r -= (float)h;
+    }
+  }
+}
+
+template <bool F16>
+__device__ inline f16v mfma(u8v a, u8v b, f16v acc) {
+  // a: 8 basis values (rows n), b: 8 coefficient values (columns w)
+  if constexpr (F16)
+    return __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(h8, a), __builtin_bit_cast(h8, b), acc, 0, 0, 0);
+  else
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(b8, a), __builtin_bit_cast(b8, b), acc, 0, 0,
+                                                   0);
+}
+
+// S = Kp / 16 k-steps (Kp = E rounded up to 16), NT = N / 32 output row tiles.
+// LDS bytes of one instantiation: basis pieces, tables, per-wave staging.
+__host__ __device__ constexpr size_t mfma_lds_bytes(int bpieces, int N, int Kp, int n_books, int n_rows, int E,
+                                                    bool stage) {
+  return (size_t)bpieces * N * (Kp + 8) * 2 + (size_t)n_books * n_rows * 256 * 5 + (size_t)n_books * E + 16 +
+         (stage ? (size_t)(kThreads / 64) * (kTileWindows * N + 4) * 4 : 0);
+}
+
+// Whether an instantiation stages its outputs (decided for the largest tables).
+template <int PREC, int S, int NT>
+constexpr bool kStage = mfma_lds_bytes(Traits<PREC>::kBPieces, NT * 32, S * 16, kMaxBooks, kMaxRows, S * 16, true) <=
+                        160 * 1024;
+
+template <int PREC, int S, int NT, bool STAGE>
+__global__ void __launch_bounds__(kThreads) k_dqidct_mfma(fptc_batch b, int E, int n_books, int n_rows,
+                                                          const float *deq_val, const uint8_t *deq_zone,
+                                                          const uint8_t *row_of_bin, const float *basis,
+                                                          const int64_t *hdr, const int64_t *win_off,
+                                                          const int32_t *tile_stream, const uint8_t *symbols,
+                                                          const float *gamma, float *out) {
+  using T = Traits<PREC>;
+  constexpr int N = NT * 32, Kp = S * 16, KH = Kp / 2;
+  constexpr int RS = Kp + 8;  // LDS row stride of a basis piece, in halves
+  constexpr int BP = T::kBPieces, AP = T::kAPieces;
+  extern __shared__ __align__(16) unsigned char lds[];
+  uint16_t *Bs = reinterpret_cast<uint16_t *>(lds);                         // [BP][N][RS]
+  float *Tv = reinterpret_cast<float *>(lds + (size_t)BP * N * RS * 2);      // [books][rows][256]
+  uint8_t *Tz = reinterpret_cast<uint8_t *>(Tv + n_books * n_rows * 256);    // [books][rows][256]
+  uint8_t *Rb = Tz + n_books * n_rows * 256;                                 // [books][E]
+
+  // Stage the split basis (transposed to [n][k], zero beyond E) and the tables.
+  const float bscale = T::kF16 ? kBasisScaleF16 : 1.0f;
+  for (int i = threadIdx.x; i < N * Kp; i += kThreads) {
+    const int n = i / Kp, k = i % Kp;
+    const float v = k < E ? basis[(int64_t)k * N + n] * bscale : 0.0f;
+    uint16_t pc[BP];
+    split<T::kF16, BP>(v, pc);
+#pragma unroll
+    for (int p = 0; p < BP; ++p) Bs[(p * N + n) * RS + k] = pc[p];
+  }
+  for (int i = threadIdx.x; i < n_books * n_rows * 256; i += kThreads) {
+    Tv[i] = deq_val[i];
+    const int z = deq_zone[i];
+    Tz[i] = (uint8_t)(z < 2 ? z : 2);
+  }
+  for (int i = threadIdx.x; i < n_books * E; i += kThreads) {
+    const int r = row_of_bin[i];
+    Rb[i] = (uint8_t)(r < n_rows ? r : n_rows - 1);
+  }
+  __syncthreads();
+
+  const int lane = threadIdx.x & 63, col = lane & 31, h = lane >> 5;
+  const int wid = threadIdx.x >> 6;
+  const int64_t n_win = hdr[1];
+  const int64_t n_tiles = (n_win + kTileWindows - 1) / kTileWindows;
+  const int64_t stride = (int64_t)gridDim.x * (kThreads / 64);
+  const float oscale = 1.0f / bscale;
+  const bool e_vec = (E % 16) == 0;
+
+  for (int64_t tile = (int64_t)blockIdx.x * (kThreads / 64) + wid; tile < n_tiles; tile += stride) {
+    // ---- window of this lane's column
+    const int64_t g = tile * kTileWindows + col;
+    int valid = 0, book = 0;
+    int64_t obase = 0;
+    float gz0 = 1.0f, gz1 = 1.0f, gz2 = 1.0f;
+    if (g < n_win) {
+      int s = tile_stream[tile];
+      s = s < 0 ? 0 : (s >= b.n_streams ? b.n_streams - 1 : s);
+      while (s + 1 < b.n_streams && win_off[s + 1] <= g) ++s;
+      const int64_t j = g - win_off[s];
+      const int64_t L = b.sample_off[s + 1] - b.sample_off[s];
+      const int64_t o = b.sample_off[s] + j * N;
+      int64_t v = L - j * N;
+      v = v < N ? v : N;
+      if (o < 0 || o + v > b.n_samples || j < 0) v = 0;
+      valid = v > 0 ? (int)v : 0;
+      obase = o;
+      const int bk = b.book_id ? (int)b.book_id[s] : 0;
+      book = bk < n_books ? bk : 0;
+      if (gamma) {
+        gz0 = gamma[3 * (int64_t)s];
+        gz1 = gamma[3 * (int64_t)s + 1];
+        gz2 = gamma[3 * (int64_t)s + 2];
+      }
+    }
+    // ---- coefficients of this lane: bins h*KH + [0, KH), split into pieces
+    u8v A[AP][S];
+    bool a_rest = false;  // any nonzero lower piece in this lane
+    {
+      const int64_t sbase = g * (int64_t)E + h * KH;
+      const uint8_t *rb = Rb + book * E;
+      const float *tv = Tv + book * n_rows * 256;
+      const uint8_t *tz = Tz + book * n_rows * 256;
+#pragma unroll
+      for (int s = 0; s < S; ++s) {
+        uint8_t sy[8];
+        const int k0 = h * KH + 8 * s;
+        if (valid > 0 && e_vec && k0 + 8 <= E && sbase + 8 * s + 8 <= b.n_symbols) {
+          const uint2 u = *reinterpret_cast<const uint2 *>(symbols + sbase + 8 * s);
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            sy[j] = (uint8_t)(u.x >> (8 * j));
+            sy[4 + j] = (uint8_t)(u.y >> (8 * j));
+          }
+        } else {
+#pragma unroll
+          for (int j = 0; j < 8; ++j) {
+            const int64_t si = sbase + 8 * s + j;
+            sy[j] = (valid > 0 && k0 + j < E && si < b.n_symbols) ? symbols[si] : (uint8_t)128;
+          }
+        }
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          const int k = k0 + j;
+          float c = 0.0f;
+          if (valid > 0 && k < E) {
+            const int ti = rb[k] * 256 + sy[j];
+            c = tv[ti];
+            if (gamma) {
+              const int z = tz[ti];
+              c *= z == 0 ? gz0 : (z == 1 ? gz1 : gz2);
+            }
+          }
+          uint16_t pc[AP];
+          split<T::kF16, AP>(c, pc);
+#pragma unroll
+          for (int p = 0; p < AP; ++p) A[p][s][j] = pc[p];
+#pragma unroll
+          for (int p = 1; p < AP; ++p) a_rest |= (pc[p] & 0x7fff) != 0;
+        }
+      }
+    }
+    const bool any_rest = AP > 1 && __any(a_rest);
+
+    // ---- output placement.  Windows are stored in global order with their
+    // padding dropped, so a tile's valid samples normally form one contiguous
+    // run [A0, A0 + R): stage them in LDS by output address and store the run
+    // on the destination's 16-byte grid.  A tile that is not contiguous (only
+    // possible with corrupt headers) is stored element by element.
+    const int64_t oend = obase + valid;
+    const int64_t prev_end = __shfl(oend, (col + 31) & 31 | (h << 5), 64);
+    const int prev_valid = __shfl(valid, (col + 31) & 31 | (h << 5), 64);
+    const bool link_ok = valid == 0 || col == 0 || (prev_valid > 0 && obase == prev_end);
+    const bool staged = STAGE && __all(link_ok);
+    const int64_t A0 = __shfl(obase, 0, 64);
+    const int m = (int)((reinterpret_cast<uintptr_t>(out + A0) >> 2) & 3);
+    float *stage = reinterpret_cast<float *>(Rb + n_books * E + 15 - ((uintptr_t)(Rb + n_books * E + 15) & 15)) +
+                   (size_t)wid * (kTileWindows * N + 4);
+
+    // ---- contraction, one 32-row output tile at a time
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      f16v acc;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
+      const uint16_t *brow = Bs + (t * 32 + col) * RS + h * KH;
+#pragma unroll
+      for (int s = 0; s < S; ++s) {
+        u8v bp[BP];
+#pragma unroll
+        for (int p = 0; p < BP; ++p) bp[p] = *reinterpret_cast<const u8v *>(brow + p * N * RS + 8 * s);
+        // smallest terms first
+        if constexpr (BP == 3) {
+          acc = mfma<T::kF16>(bp[2], A[0][s], acc);
+          if (any_rest) {
+            acc = mfma<T::kF16>(bp[1], A[1][s], acc);
+            acc = mfma<T::kF16>(bp[0], A[2][s], acc);
+          }
+          acc = mfma<T::kF16>(bp[1], A[0][s], acc);
+          if (any_rest) acc = mfma<T::kF16>(bp[0], A[1][s], acc);
+        } else if constexpr (BP == 2) {
+          if (any_rest) acc = mfma<T::kF16>(bp[0], A[1][s], acc);
+          acc = mfma<T::kF16>(bp[1], A[0][s], acc);
+        }
+        acc = mfma<T::kF16>(bp[0], A[0][s], acc);
+      }
+      // lane holds rows n = t*32 + 8*q + 4*h + (0..3) of column w = col
+      if (valid > 0) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int n0 = t * 32 + 8 * q + 4 * h;
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            if (n0 + i < valid) {
+              const float v = acc[4 * q + i] * oscale;
+              if (staged) stage[obase - A0 + n0 + i + m] = v;
+              else out[obase + n0 + i] = v;
+            }
+          }
+        }
+      }
+    }
+    if (staged) {
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      // run length: end of the last window with samples
+      int last = 31;
+      const uint64_t has = __ballot(valid > 0);
+      last = has ? 63 - __builtin_clzll(has & 0xffffffffull) : -1;
+      if (last >= 0) {
+        const int64_t R = __shfl(oend, last, 64) - A0;
+        float *dst = out + A0 - m;  // 16-byte aligned
+        const int nblk = (int)((m + R + 3) >> 2);
+        for (int k = lane; k < nblk; k += 64) {
+          const int lo = 4 * k;
+          if (lo >= m && lo + 4 <= m + R) {
+            *reinterpret_cast<float4 *>(dst + lo) = *reinterpret_cast<const float4 *>(stage + lo);
+          } else {
+            for (int j = lo; j < lo + 4; ++j)
+              if (j >= m && j < m + R) dst[j] = stage[j];
+          }
+        }
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+  }
+}
+
+template <int PREC, int S, int NT>
+int launch_t(const fptc_batch &b, const fptc_codec &c, const Shape &sh, const Plan &p, const uint8_t *symbols,
+             const float *gamma, float *out, void *stream) {
+  constexpr int N = NT * 32, Kp = S * 16;
+  constexpr bool stage = kStage<PREC, S, NT>;
+  const size_t lds = mfma_lds_bytes(Traits<PREC>::kBPieces, N, Kp, c.n_books, c.n_rows, c.E, stage);
+  auto kern = k_dqidct_mfma<PREC, S, NT, stage>;
+  static bool attr_set = false;  // one attribute call per instantiation
+  if (!attr_set) {
+    if (hipFuncSetAttribute(reinterpret_cast<const void *>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
+                            160 * 1024) != hipSuccess)
+      return (int)hipErrorInvalidValue;
+    attr_set = true;
+  }
+  int blocks = sh.blocks > 0 ? sh.blocks : device_cu_count() * 2;
+  hipLaunchKernelGGL(kern, dim3(blocks), dim3(kThreads), lds, (hipStream_t)stream, b, c.E, c.n_books, c.n_rows,
+                     c.deq_val, c.deq_zone, c.row_of_bin, c.basis, p.hdr, p.win_off, p.tile_stream, symbols, gamma,
+                     out);
+  return (int)hipGetLastError();
+}
+
+template <int PREC>
+int launch_prec(const fptc_batch &b, const fptc_codec &c, const Shape &sh, const Plan &p, const uint8_t *symbols,
+                const float *gamma, float *out, void *stream) {
+  const int S = (c.E + 15) / 16;
+#define FPTC_CASE(NV, SV) \
+  if (c.N == NV && S == SV) return launch_t<PREC, SV, NV / 32>(b, c, sh, p, symbols, gamma, out, stream);
+  FPTC_CASE(32, 1) FPTC_CASE(32, 2)
+  FPTC_CASE(64, 1) FPTC_CASE(64, 2) FPTC_CASE(64, 3) FPTC_CASE(64, 4)
+  FPTC_CASE(128, 1) FPTC_CASE(128, 2) FPTC_CASE(128, 3) FPTC_CASE(128, 4)
+  FPTC_CASE(128, 5) FPTC_CASE(128, 6) FPTC_CASE(128, 7) FPTC_CASE(128, 8)
+#undef FPTC_CASE
+  return (int)hipErrorInvalidValue;
+}
+
+}  // namespace
+
+bool mfma_supported(int N, int E, int precision) {
+  if (precision < FPTC_FP16 || precision > FPTC_BF16X3) return false;
+  if (N != 32 && N != 64 && N != 128) return false;
+  if (E < 1 || E > N) return false;
+  // LDS: basis pieces + tables must fit in 160 KB (staging is optional)
+  const int Kp = (E + 15) / 16 * 16;
+  const int pieces = precision == FPTC_BF16X3 ? 3 : (precision == FPTC_FP16X2 ? 2 : 1);
+  return mfma_lds_bytes(pieces, N, Kp, kMaxBooks, kMaxRows, E, false) <= 160 * 1024;
+}
+
+int launch_dqidct_mfma(const fptc_batch &b, const fptc_codec &c, const Shape &s, const Plan &p,
+                       const uint8_t *symbols, const float *gamma, int precision, float *out, void *stream) {
+  switch (precision) {
+    case FPTC_FP16: return launch_prec<FPTC_FP16>(b, c, s, p, symbols, gamma, out, stream);
+    case FPTC_FP16X2: return launch_prec<FPTC_FP16X2>(b, c, s, p, symbols, gamma, out, stream);
+    case FPTC_BF16: return launch_prec<FPTC_BF16>(b, c, s, p, symbols, gamma, out, stream);
+    case FPTC_BF16X3: return launch_prec<FPTC_BF16X3>(b, c, s, p, symbols, gamma, out, stream);
+    default: return (int)hipErrorInvalidValue;
+  }
+}
+
+}  // namespace fptc

@@ -15,6 +15,7 @@ constexpr int kDefaultWavesPerBlock = 4;
 constexpr int kMaxBooks = 8;
 constexpr int kMaxRows = 4;
 constexpr int kMaxLmax = 12;
+constexpr int kTileWindows = 32;  // windows per MFMA tile (one 32x32 output block per wave)
 
 // Resolved launch shape (defaults applied, validated).
 struct Shape {
@@ -30,9 +31,10 @@ struct Shape {
 //   chunk_word int64[cap]   global index of the first word holding a symbol of the chunk, -1 if none
 //   chunk_wsym int64[cap]   in-stream index of that word's first symbol
 //   bwd_part   double[cap*3] backward partial sums per chunk and zone
+//   tile_stream int32[tcap] stream owning the first window of each 32-window tile
 struct Layout {
-  size_t hdr, win_off, chunk_off, chunk_word, chunk_wsym, bwd_part, total;
-  int64_t chunk_cap;
+  size_t hdr, win_off, chunk_off, chunk_word, chunk_wsym, bwd_part, tile_stream, total;
+  int64_t chunk_cap, tile_cap;
 };
 
 Layout layout_for(const fptc_batch *b, const fptc_codec *c, const Shape &s);
@@ -45,7 +47,8 @@ struct Plan {
   int64_t *chunk_word;
   int64_t *chunk_wsym;
   double *bwd_part;
-  int64_t chunk_cap;
+  int32_t *tile_stream;
+  int64_t chunk_cap, tile_cap;
 };
 
 Plan plan_view(void *ws, const Layout &L);
@@ -57,6 +60,10 @@ int launch_decode(const fptc_batch &b, const fptc_codec &c, const Shape &s, cons
                   int32_t *status, void *stream);
 int launch_dqidct(const fptc_batch &b, const fptc_codec &c, const Shape &s, const Plan &p,
                   const uint8_t *symbols, const float *gamma, int precision, float *out, void *stream);
+
+bool mfma_supported(int N, int E, int precision);
+int launch_dqidct_mfma(const fptc_batch &b, const fptc_codec &c, const Shape &s, const Plan &p,
+                       const uint8_t *symbols, const float *gamma, int precision, float *out, void *stream);
 
 int device_cu_count();
 

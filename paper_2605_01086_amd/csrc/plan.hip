@@ -95,9 +95,17 @@ __global__ void __launch_bounds__(kPlanThreads) k_plan_streams(fptc_batch b, int
 __global__ void __launch_bounds__(kScanThreads) k_plan_chunks(fptc_batch b, int N, int E, int wpc,
                                                               const int64_t *win_off, const int64_t *chunk_off,
                                                               int64_t *chunk_word, int64_t *chunk_wsym,
+                                                              int32_t *tile_stream, int64_t tile_cap,
                                                               int32_t *status) {
   __shared__ int64_t lds[kScanThreads / kWave + 1];
   const int s = blockIdx.x;
+  // Every stream, valid or not, records itself as the owner of the 32-window
+  // tiles whose first window it holds, so a tile's first stream is one load.
+  {
+    const int64_t t0 = (win_off[s] + kTileWindows - 1) / kTileWindows;
+    const int64_t t1 = (win_off[s + 1] + kTileWindows - 1) / kTileWindows;
+    for (int64_t t = t0 + threadIdx.x; t < t1 && t < tile_cap; t += kScanThreads) tile_stream[t] = s;
+  }
   const int64_t c0 = chunk_off[s], nc = chunk_off[s + 1] - c0;
   if (nc <= 0) return;  // empty stream or bad header (then status already flagged)
   for (int64_t i = threadIdx.x; i < nc; i += kScanThreads) chunk_word[c0 + i] = -1;
@@ -153,7 +161,7 @@ int launch_plan(const fptc_batch &b, const fptc_codec &c, const Shape &s, const 
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return (int)e;
   hipLaunchKernelGGL(k_plan_chunks, dim3(b.n_streams), dim3(kScanThreads), 0, st, b, c.N, c.E, s.wpc, p.win_off,
-                     p.chunk_off, p.chunk_word, p.chunk_wsym, status);
+                     p.chunk_off, p.chunk_word, p.chunk_wsym, p.tile_stream, p.tile_cap, status);
   return (int)hipGetLastError();
 }
 

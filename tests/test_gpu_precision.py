@@ -1,0 +1,58 @@
+"""GPU parity of the MFMA dequant+IDCT variants against the FP64 oracle.
+
+FP16X2 and BF16X3 (split operands, FP32 accumulation) must meet the same
+1e-5 range-relative bound as the FP32 path; single-pass FP16 and BF16 are
+reported and held to the bound their 11- and 8-bit significands allow."""
+import numpy as np
+import pytest
+
+from cases import build_case, paper_params
+from gpu_helpers import check_parity, run_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+def _amp(N, E=None, **kw):
+    from oracle import oracle as O
+    return O.QuantParams("amp", N, N if E is None else E, **kw)
+
+
+# (precision, tolerance on max |err| / range)
+EXACT = [("fp16x2", 1e-5), ("bf16x3", 1e-5)]
+LOOSE = [("fp16", 2e-3), ("bf16", 2e-2)]
+
+
+@pytest.mark.parametrize("prec,tol", EXACT + LOOSE)
+@pytest.mark.parametrize("N", [32, 64, 128])
+def test_mfma_variants_amplitude(prec, tol, N):
+    rng = np.random.default_rng(N)
+    lens = list(np.floor(2.0 ** rng.uniform(5, 13, size=12)).astype(int)) + [1, N - 1, N + 1, 33 * N]
+    c = build_case(_amp(N), ["eeg", "seismic", "power", "meteo"], lens, config_id=1000 + N)
+    worst = check_parity(c, run_gpu(c, precision=prec), tol=tol)
+    print(f"{prec} N={N}: worst range-relative error {worst:.3e}")
+
+
+@pytest.mark.parametrize("prec,tol", EXACT)
+@pytest.mark.parametrize("N,E", [(32, 16), (64, 20), (64, 64), (128, 100)])
+def test_mfma_variants_paper_quantizer_and_scales(prec, tol, N, E):
+    # inexact dequantized values (mu-law) and per-zone scales exercise the coefficient split
+    p = paper_params(N, E, "eeg", 1100 + N)
+    c = build_case(p, ["eeg", "meteo"], [N * 150 + 7, 3001, 5, N * 31], config_id=1100 + N, gamma=True)
+    worst = check_parity(c, run_gpu(c, precision=prec), tol=tol)
+    print(f"{prec} N={N} E={E}: worst range-relative error {worst:.3e}")
+
+
+@pytest.mark.parametrize("prec", ["fp16x2", "bf16x3"])
+def test_mfma_large_coarse_quantizer(prec):
+    # steps 1.0 / 8.0: coefficient values up to 904
+    c = build_case(_amp(64, step_f=1.0, step_c=8.0, T=16.0), ["eeg"], [1 << 16, 12345], config_id=1200)
+    check_parity(c, run_gpu(c, precision=prec), tol=1e-5)
+
+
+def test_mfma_matches_fp32_path_bitwise_symbols():
+    # the contraction variant never changes the decoded symbols
+    c = build_case(_amp(64), ["eeg", "seismic"], [5000, 7000], config_id=1300)
+    a = run_gpu(c, precision="fp32")
+    b = run_gpu(c, precision="fp16x2")
+    assert np.array_equal(a["sym"], b["sym"])
+    assert np.max(np.abs(a["out"] - b["out"])) <= 1e-5 * np.ptp(np.concatenate(c.recon))
