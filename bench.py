@@ -91,10 +91,12 @@ def encode(x, sample_off, dom, train, q, threads):
     return wc, sc, word_off, lens_tab
 
 
-def time_batched(dec, steps, warmup, precision):
+def time_batched(dec, steps, warmup, precision, fused=False):
+    """Per step: plan, then the fused kernel or decode + dequant/IDCT.
+    Returns host ms/step, mean HIP-event ms of each stage, per-step GPU ms."""
     import torch
     for _ in range(warmup):
-        dec.run(precision=precision)
+        dec.run(precision=precision, fused=fused)
     torch.cuda.synchronize()
     ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(steps)]
     t0 = time.perf_counter()
@@ -103,9 +105,13 @@ def time_batched(dec, steps, warmup, precision):
         e[0].record()
         dec.plan()
         e[1].record()
-        dec.decode()
-        e[2].record()
-        dec.dequant_idct(precision=precision)
+        if fused:
+            dec.decompress(precision=precision)
+            e[2].record()
+        else:
+            dec.decode()
+            e[2].record()
+            dec.dequant_idct(precision=precision)
         e[3].record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -202,9 +208,11 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="batch", choices=["batch", "plain"])
-    ap.add_argument("--precision", default="fp32")
+    ap.add_argument("--precision", default="fp16x2", choices=["fp32", "fp16", "fp16x2", "bf16", "bf16x3"])
+    ap.add_argument("--path", default="fused", choices=["fused", "split"],
+                    help="fused: one decode+dequant+IDCT kernel; split: decode kernel then dequant+IDCT kernel")
     ap.add_argument("--wpc", type=int, default=32)
-    ap.add_argument("--waves", type=int, default=4)
+    ap.add_argument("--waves", type=int, default=8)
     ap.add_argument("--blocks", type=int, default=0)
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -233,7 +241,10 @@ def main():
     batch = C.DeviceBatch(words, symlen, word_off, sample_off, q.N, q.E, dom if args.workload == "batch" else None)
     launch = C.Launch(args.wpc, args.waves, args.blocks)
     dec = C.Decoder(batch, codec, launch)
-    ms_step, per_kernel, gpu_steps = time_batched(dec, args.steps, args.warmup, args.precision)
+    fused = args.path == "fused"
+    if fused and args.precision == "fp32":
+        raise SystemExit("the fused path runs the MFMA precisions (fp16x2, bf16x3, fp16, bf16)")
+    ms_step, per_kernel, gpu_steps = time_batched(dec, args.steps, args.warmup, args.precision, fused)
     status = dec.status.cpu().numpy()
     if np.any(status != 0):
         raise SystemExit(f"decode reported stream errors: {np.flatnonzero(status)[:8]}")
@@ -241,28 +252,38 @@ def main():
     out_bytes = 4 * n_samples
     value = out_bytes / (ms_step * 1e-3) / 1e9
     comp_bytes = batch.compressed_bytes + batch.header_bytes
-    # algorithmic bytes per launch of each kernel (measurement)
-    alg = {"plan": batch.n_words + batch.header_bytes,
-           "decode": batch.compressed_bytes + batch.header_bytes + batch.n_symbols,
-           "dequant_idct": batch.n_symbols + out_bytes}
-    names = ["plan", "decode", "dequant_idct"]
-    dom_k = int(np.argmax(per_kernel))
+    # algorithmic bytes of one launch of each stage (measurement):
+    # compressed words 8 B + symlen 1 B per word, per-stream headers, 1 B per
+    # decoded symbol written or read between the split kernels, 4 B per sample.
+    if fused:
+        names = ["plan", "fused"]
+        stage_ms = per_kernel[:2]
+        alg = {"plan": batch.n_words + batch.header_bytes, "fused": comp_bytes + out_bytes}
+        kern = {"plan": "k_plan_chunks", "fused": f"k_fused<{args.precision}>"}
+    else:
+        names = ["plan", "decode", "dequant_idct"]
+        stage_ms = per_kernel
+        alg = {"plan": batch.n_words + batch.header_bytes, "decode": comp_bytes + batch.n_symbols,
+               "dequant_idct": batch.n_symbols + out_bytes}
+        kern = {"plan": "k_plan_chunks", "decode": "k_decode",
+                "dequant_idct": "k_dqidct_f32" if args.precision == "fp32" else f"k_dqidct_mfma<{args.precision}>"}
+    dom_k = int(np.argmax(stage_ms))
     kname = names[dom_k]
-    achieved = alg[kname] / (per_kernel[dom_k] * 1e-3) / 1e9
-    roof = {"bound": "hbm", "kernel": {"decode": "k_decode", "dequant_idct": "k_dqidct_f32",
-                                       "plan": "k_plan_chunks"}[kname],
-            "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None}
+    achieved = alg[kname] / (stage_ms[dom_k] * 1e-3) / 1e9
+    roof = {"bound": "hbm", "kernel": kern[kname], "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "algorithmic_bytes": int(alg[kname]), "avg_ms": round(float(stage_ms[dom_k]), 4)}
     path_alg = comp_bytes + out_bytes
     path_roofline_decoded = HBM_PEAK_GBS * out_bytes / path_alg
     line = {
         "metric": "decoded GB/s (float32 output) + % HBM roofline, batched vs plain, at 1 MI355X",
         "value": round(value, 2), "unit": "GB/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(ms_step, 4), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32", "data": "synthetic",
+        "dtype": "f32" if args.precision == "fp32" else f"{args.precision} MFMA, f32 accumulate",
+        "data": "synthetic",
         "config": {"workload": f"fptc-{args.workload}", "streams": int(len(sample_off) - 1),
                    "samples": n_samples, "window": q.N, "kept_coeffs": q.E, "quantizer": "amplitude 0.25/2.0/T16",
-                   "lmax": 12, "precision": args.precision, "windows_per_chunk": args.wpc,
+                   "lmax": 12, "path": args.path, "precision": args.precision, "windows_per_chunk": args.wpc,
                    "waves_per_block": args.waves, "compressed_bytes": int(comp_bytes),
                    "bytes_per_sample_in": round(comp_bytes / n_samples, 4)},
         "roofline": roof,
@@ -270,16 +291,19 @@ def main():
                           "frac": round(path_alg / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                           "roofline_decoded_GBs": round(path_roofline_decoded, 1),
                           "decoded_frac_of_roofline": round(value / path_roofline_decoded, 4)},
-        "kernel_ms": {k: round(float(v), 4) for k, v in zip(names, per_kernel)},
+        "stage_ms": {k: round(float(v), 4) for k, v in zip(names, stage_ms)},
         "gpu_ms_per_step": {"median": round(float(np.median(gpu_steps)), 4), "min": round(float(gpu_steps.min()), 4),
                             "max": round(float(gpu_steps.max()), 4)},
     }
     if not args.no_per_stream and args.workload == "batch":
-        ms_ps, out_ps = time_per_stream(batch, codec, launch, 3, args.precision)
-        same = bool(torch.equal(out_ps[:n_samples], dec.out[:n_samples]))
-        line["per_stream_launches"] = {"value": round(out_bytes / (ms_ps * 1e-3) / 1e9, 2), "unit": "GB/s",
-                                       "ms_per_step": round(ms_ps, 3), "launches_per_step": 4 * batch.n_streams,
-                                       "bitwise_equal_to_batched": same}
+        # the plain decoder: FP32 SIMT dequant+IDCT, one launch sequence per stream
+        ms_ps, out_ps = time_per_stream(batch, codec, C.Launch(args.wpc, 4, 0), 3, "fp32")
+        a, bref = out_ps[:n_samples], dec.out[:n_samples]
+        rel = float((a - bref).abs().max() / (bref.max() - bref.min()))
+        line["plain_per_stream_fp32"] = {"value": round(out_bytes / (ms_ps * 1e-3) / 1e9, 2), "unit": "GB/s",
+                                         "ms_per_step": round(ms_ps, 3), "launches_per_step": 4 * batch.n_streams,
+                                         "max_abs_diff_vs_batched_over_range": rel,
+                                         "batched_speedup": round(ms_ps / ms_step, 2)}
     if not args.no_cpu_baseline:
         done, dt = cpu_baseline(words, symlen, word_off, sample_off, dom, lens_tab, q, args.cpu_budget, threads)
         line["cpu_baseline"] = {"value": round(4 * done["samples"] / dt / 1e9, 5), "unit": "GB/s", "cores": threads,

@@ -115,7 +115,8 @@ typedef struct {
 /* Launch shape.  Zero fields take the library defaults. */
 typedef struct {
   int32_t windows_per_chunk;  /* windows per decode work item (chunk); default 32 */
-  int32_t waves_per_block;    /* default 4 */
+  int32_t waves_per_block;    /* 0: default (4; fptc_decompress_batch: the most, up to 12,
+                                 whose LDS fits); at most 16 (12 for fptc_decompress_batch) */
   int32_t blocks;             /* persistent grid size; default: enough to fill the GPU */
   int32_t reserved0;
 } fptc_launch;
@@ -176,6 +177,17 @@ FPTC_API int32_t fptc_decode_batch(const fptc_batch *batch, const fptc_codec *co
 FPTC_API int32_t fptc_dequant_idct(const fptc_batch *batch, const fptc_codec *codec, const fptc_launch *launch,
                           const void *ws, size_t ws_bytes, const uint8_t *symbols, const float *gamma,
                           int32_t precision, float *out, void *stream);
+
+/* Decode, dequantize and inverse-transform in one pass: the two stages of
+ * Section 4.2 fused, the decoded symbols of a chunk of windows kept in LDS
+ * instead of a global array.  Same result as fptc_decode_batch followed by
+ * fptc_dequant_idct with the same precision (bit-identical samples), without
+ * the symbol array.  Precisions: the MFMA ones (FP16, FP16X2, BF16, BF16X3)
+ * for N in {32, 64, 128}; FPTC_ERR_UNSUPPORTED otherwise.  Needs a plan in
+ * `ws`; decoding errors OR into stream_status (device [n_streams]). */
+FPTC_API int32_t fptc_decompress_batch(const fptc_batch *batch, const fptc_codec *codec, const fptc_launch *launch,
+                                       const void *ws, size_t ws_bytes, const float *gamma, int32_t precision,
+                                       float *out, int32_t *stream_status, void *stream);
 
 /* ------------------------------------------------------------ host calls */
 

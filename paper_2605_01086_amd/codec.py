@@ -106,7 +106,7 @@ class DeviceBatch:
 @dataclass
 class Launch:
     windows_per_chunk: int = 32
-    waves_per_block: int = 4
+    waves_per_block: int = 0  # 0 = library default
     blocks: int = 0
 
     def c(self) -> F.fptc_launch:
@@ -141,8 +141,16 @@ class Decoder:
         F.fptc_dequant_idct(self.batch.c, self.codec.c, self.lc, self.ws, self.symbols, gamma, precision, out)
         return out[: self.batch.n_samples]
 
-    def run(self, gamma=None, precision="fp32"):
+    def decompress(self, gamma=None, precision="fp16x2", out=None):
+        """Fused decode + dequant + IDCT (needs a plan)."""
+        out = self.out if out is None else out
+        F.fptc_decompress_batch(self.batch.c, self.codec.c, self.lc, self.ws, gamma, precision, out, self.status)
+        return out[: self.batch.n_samples]
+
+    def run(self, gamma=None, precision="fp32", fused=False):
         self.plan()
+        if fused:
+            return self.decompress(gamma, precision)
         self.decode()
         return self.dequant_idct(gamma, precision)
 

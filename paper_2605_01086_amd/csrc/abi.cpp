@@ -36,6 +36,7 @@ int check_codec(const fptc_codec *c) {
 int resolve_shape(const fptc_launch *l, const fptc_codec *c, Shape *s) {
   s->wpc = (l && l->windows_per_chunk) ? l->windows_per_chunk : kDefaultWindowsPerChunk;
   s->waves = (l && l->waves_per_block) ? l->waves_per_block : kDefaultWavesPerBlock;
+  s->auto_waves = !(l && l->waves_per_block);
   s->blocks = l ? l->blocks : 0;
   if (s->wpc < 1 || s->wpc > 1024 || s->waves < 1 || s->waves > 16 || s->blocks < 0) return FPTC_ERR_INVALID_ARG;
   // LDS budget of the decode kernel: lookup tables + one symbol buffer per wave.
@@ -70,6 +71,8 @@ Layout layout_for(const fptc_batch *b, const fptc_codec *c, const Shape &s) {
   L.tile_cap = (max_windows + kTileWindows - 1) / kTileWindows + 1;
   L.tile_stream = off;
   off = align256(off + L.tile_cap * sizeof(int32_t));
+  L.chunk_meta = off;
+  off = align256(off + L.chunk_cap * sizeof(ChunkMeta));
   L.total = off;
   return L;
 }
@@ -84,6 +87,7 @@ Plan plan_view(void *ws, const Layout &L) {
   v.chunk_wsym = reinterpret_cast<int64_t *>(p + L.chunk_wsym);
   v.bwd_part = reinterpret_cast<double *>(p + L.bwd_part);
   v.tile_stream = reinterpret_cast<int32_t *>(p + L.tile_stream);
+  v.chunk_meta = reinterpret_cast<ChunkMeta *>(p + L.chunk_meta);
   v.chunk_cap = L.chunk_cap;
   v.tile_cap = L.tile_cap;
   return v;
@@ -156,6 +160,27 @@ int32_t fptc_dequant_idct(const fptc_batch *batch, const fptc_codec *codec, cons
   if (precision == FPTC_FP32_SIMT)
     return status_of(launch_dqidct(*batch, *codec, s, pv, symbols, gamma, precision, out, stream));
   return status_of(launch_dqidct_mfma(*batch, *codec, s, pv, symbols, gamma, precision, out, stream));
+}
+
+int32_t fptc_decompress_batch(const fptc_batch *batch, const fptc_codec *codec, const fptc_launch *launch,
+                              const void *ws, size_t ws_bytes, const float *gamma, int32_t precision, float *out,
+                              int32_t *stream_status, void *stream) {
+  Shape s;
+  int rc;
+  if ((rc = check_batch(batch)) || (rc = check_codec(codec)) || (rc = resolve_shape(launch, codec, &s))) return rc;
+  if (!ws || (!out && batch->n_samples > 0)) return FPTC_ERR_INVALID_ARG;
+  if (precision < FPTC_FP32_SIMT || precision > FPTC_BF16X3) return FPTC_ERR_INVALID_ARG;
+  if (s.auto_waves) {  // the most waves (up to 12) whose LDS fits
+    s.waves = 12;
+    while (s.waves > 1 && !fused_supported(codec->N, codec->E, precision, s.wpc, s.waves, codec->n_books, codec->n_rows, codec->lmax))
+      --s.waves;
+  }
+  if (!fused_supported(codec->N, codec->E, precision, s.wpc, s.waves, codec->n_books, codec->n_rows, codec->lmax))
+    return FPTC_ERR_UNSUPPORTED;
+  Layout L = layout_for(batch, codec, s);
+  if (ws_bytes < L.total) return FPTC_ERR_WORKSPACE;
+  return status_of(launch_fused(*batch, *codec, s, plan_view(const_cast<void *>(ws), L), gamma, precision, out,
+                                stream_status, stream));
 }
 
 }  // extern "C"

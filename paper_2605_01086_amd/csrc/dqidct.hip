@@ -95,7 +95,9 @@ __global__ void __launch_bounds__(kThreads) k_dqidct_f32(fptc_batch b, int N, in
 #pragma unroll
     for (int r = 0; r < kPerThread; ++r) acc[r] = 0.0f;
 
-    for (int kb = 0; kb < E; kb += kKB) {
+    // bins from the highest down: the DC term, often a large offset, enters
+    // the FP32 sums last
+    for (int kb = ((E - 1) / kKB) * kKB; kb >= 0; kb -= kKB) {
       const int kn = min(kKB, E - kb);
       __syncthreads();  // wi ready; previous block's LDS reads done
       for (int i = t; i < kKB * N; i += kThreads) {
@@ -120,7 +122,7 @@ __global__ void __launch_bounds__(kThreads) k_dqidct_f32(fptc_batch b, int N, in
         Cs[i] = v;
       }
       __syncthreads();
-      for (int k = 0; k < kn; ++k) {
+      for (int k = kn - 1; k >= 0; --k) {
         const float bv = Bs[k * N + col];
 #pragma unroll
         for (int r = 0; r < kPerThread; ++r) acc[r] = fmaf(Cs[(wrow + r * rstep) * kKB + k], bv, acc[r]);

@@ -24,70 +24,13 @@
 #include <hip/hip_runtime.h>
 
 #include "fptc_internal.h"
+#include "mfma_common.h"
 
 namespace fptc {
 namespace {
 
-typedef _Float16 h8 __attribute__((ext_vector_type(8)));
-typedef __bf16 b8 __attribute__((ext_vector_type(8)));
-typedef uint16_t u8v __attribute__((ext_vector_type(8)));  // 8 raw 16-bit operand values
-typedef float f16v __attribute__((ext_vector_type(16)));
-
 constexpr int kThreads = 256;
-constexpr float kBasisScaleF16 = 1024.0f;  // 2^10, undone exactly on the output
 
-template <int PREC>
-struct Traits;
-template <>
-struct Traits<FPTC_FP16> {
-  static constexpr int kBPieces = 1, kAPieces = 1;
-  static constexpr bool kF16 = true;
-};
-template <>
-struct Traits<FPTC_FP16X2> {
-  static constexpr int kBPieces = 2, kAPieces = 2;
-  static constexpr bool kF16 = true;
-};
-template <>
-struct Traits<FPTC_BF16> {
-  static constexpr int kBPieces = 1, kAPieces = 1;
-  static constexpr bool kF16 = false;
-};
-template <>
-struct Traits<FPTC_BF16X3> {
-  static constexpr int kBPieces = 3, kAPieces = 3;
-  static constexpr bool kF16 = false;
-};
-
-// Split x into up to P 16-bit pieces whose sum approximates x.
-template <bool F16, int P>
-__device__ inline void split(float x, uint16_t *out) {
-  float r = x;
-#pragma unroll
-  for (int i = 0; i < P; ++i) {
-    if constexpr (F16) {
-      _Float16 h = (_Float16)r;
-      out[i] = __builtin_bit_cast(uint16_t, h);
-      r -= (float)h;
-    } else {
-      __bf16 h = (__bf16)r;
-      out[i] = __builtin_bit_cast(uint16_t, h);
-      r -= (float)h;
-    }
-  }
-}
-
-template <bool F16>
-__device__ inline f16v mfma(u8v a, u8v b, f16v acc) {
-  // a: 8 basis values (rows n), b: 8 coefficient values (columns w)
-  if constexpr (F16)
-    return __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(h8, a), __builtin_bit_cast(h8, b), acc, 0, 0, 0);
-  else
-    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(b8, a), __builtin_bit_cast(b8, b), acc, 0, 0,
-                                                   0);
-}
-
-// S = Kp / 16 k-steps (Kp = E rounded up to 16), NT = N / 32 output row tiles.
 // LDS bytes of one instantiation: basis pieces, tables, per-wave staging.
 __host__ __device__ constexpr size_t mfma_lds_bytes(int bpieces, int N, int Kp, int n_books, int n_rows, int E,
                                                     bool stage) {
@@ -100,6 +43,7 @@ template <int PREC, int S, int NT>
 constexpr bool kStage = mfma_lds_bytes(Traits<PREC>::kBPieces, NT * 32, S * 16, kMaxBooks, kMaxRows, S * 16, true) <=
                         160 * 1024;
 
+// S = Kp / 16 k-steps (Kp = E rounded up to 16), NT = N / 32 output row tiles.
 template <int PREC, int S, int NT, bool STAGE>
 __global__ void __launch_bounds__(kThreads) k_dqidct_mfma(fptc_batch b, int E, int n_books, int n_rows,
                                                           const float *deq_val, const uint8_t *deq_zone,
@@ -119,14 +63,7 @@ __global__ void __launch_bounds__(kThreads) k_dqidct_mfma(fptc_batch b, int E, i
 
   // Stage the split basis (transposed to [n][k], zero beyond E) and the tables.
   const float bscale = T::kF16 ? kBasisScaleF16 : 1.0f;
-  for (int i = threadIdx.x; i < N * Kp; i += kThreads) {
-    const int n = i / Kp, k = i % Kp;
-    const float v = k < E ? basis[(int64_t)k * N + n] * bscale : 0.0f;
-    uint16_t pc[BP];
-    split<T::kF16, BP>(v, pc);
-#pragma unroll
-    for (int p = 0; p < BP; ++p) Bs[(p * N + n) * RS + k] = pc[p];
-  }
+  stage_basis<PREC>(Bs, basis, N, E, Kp, RS, threadIdx.x, kThreads);
   for (int i = threadIdx.x; i < n_books * n_rows * 256; i += kThreads) {
     Tv[i] = deq_val[i];
     const int z = deq_zone[i];
@@ -144,7 +81,7 @@ __global__ void __launch_bounds__(kThreads) k_dqidct_mfma(fptc_batch b, int E, i
   const int64_t n_tiles = (n_win + kTileWindows - 1) / kTileWindows;
   const int64_t stride = (int64_t)gridDim.x * (kThreads / 64);
   const float oscale = 1.0f / bscale;
-  const bool e_vec = (E % 16) == 0;
+  const bool e_vec = (E % 16) == 0 && (reinterpret_cast<uintptr_t>(symbols) & 7) == 0;
 
   for (int64_t tile = (int64_t)blockIdx.x * (kThreads / 64) + wid; tile < n_tiles; tile += stride) {
     // ---- window of this lane's column
@@ -172,55 +109,6 @@ __global__ void __launch_bounds__(kThreads) k_dqidct_mfma(fptc_batch b, int E, i
         gz2 = gamma[3 * (int64_t)s + 2];
       }
     }
-    // ---- coefficients of this lane: bins h*KH + [0, KH), split into pieces
-    u8v A[AP][S];
-    bool a_rest = false;  // any nonzero lower piece in this lane
-    {
-      const int64_t sbase = g * (int64_t)E + h * KH;
-      const uint8_t *rb = Rb + book * E;
-      const float *tv = Tv + book * n_rows * 256;
-      const uint8_t *tz = Tz + book * n_rows * 256;
-#pragma unroll
-      for (int s = 0; s < S; ++s) {
-        uint8_t sy[8];
-        const int k0 = h * KH + 8 * s;
-        if (valid > 0 && e_vec && k0 + 8 <= E && sbase + 8 * s + 8 <= b.n_symbols) {
-          const uint2 u = *reinterpret_cast<const uint2 *>(symbols + sbase + 8 * s);
-#pragma unroll
-          for (int j = 0; j < 4; ++j) {
-            sy[j] = (uint8_t)(u.x >> (8 * j));
-            sy[4 + j] = (uint8_t)(u.y >> (8 * j));
-          }
-        } else {
-#pragma unroll
-          for (int j = 0; j < 8; ++j) {
-            const int64_t si = sbase + 8 * s + j;
-            sy[j] = (valid > 0 && k0 + j < E && si < b.n_symbols) ? symbols[si] : (uint8_t)128;
-          }
-        }
-#pragma unroll
-        for (int j = 0; j < 8; ++j) {
-          const int k = k0 + j;
-          float c = 0.0f;
-          if (valid > 0 && k < E) {
-            const int ti = rb[k] * 256 + sy[j];
-            c = tv[ti];
-            if (gamma) {
-              const int z = tz[ti];
-              c *= z == 0 ? gz0 : (z == 1 ? gz1 : gz2);
-            }
-          }
-          uint16_t pc[AP];
-          split<T::kF16, AP>(c, pc);
-#pragma unroll
-          for (int p = 0; p < AP; ++p) A[p][s][j] = pc[p];
-#pragma unroll
-          for (int p = 1; p < AP; ++p) a_rest |= (pc[p] & 0x7fff) != 0;
-        }
-      }
-    }
-    const bool any_rest = AP > 1 && __any(a_rest);
-
     // ---- output placement.  Windows are stored in global order with their
     // padding dropped, so a tile's valid samples normally form one contiguous
     // run [A0, A0 + R): stage them in LDS by output address and store the run
@@ -236,48 +124,53 @@ __global__ void __launch_bounds__(kThreads) k_dqidct_mfma(fptc_batch b, int E, i
     float *stage = reinterpret_cast<float *>(Rb + n_books * E + 15 - ((uintptr_t)(Rb + n_books * E + 15) & 15)) +
                    (size_t)wid * (kTileWindows * N + 4);
 
-    // ---- contraction, one 32-row output tile at a time
+    // ---- contraction, one k-step at a time from the highest bins down
+    f16v acc[NT];
 #pragma unroll
-    for (int t = 0; t < NT; ++t) {
-      f16v acc;
+    for (int t = 0; t < NT; ++t)
 #pragma unroll
-      for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
-      const uint16_t *brow = Bs + (t * 32 + col) * RS + h * KH;
+      for (int r = 0; r < 16; ++r) acc[t][r] = 0.0f;
+    const int64_t sbase = g * (int64_t)E + h * KH;
+#pragma unroll 1
+    for (int s = S - 1; s >= 0; --s) {
+      const int k0 = h * KH + 8 * s;
+      uint8_t sy[8];
+      if (valid > 0 && e_vec && sbase + 8 * s + 8 <= b.n_symbols) {
+        const uint2 u = *reinterpret_cast<const uint2 *>(symbols + sbase + 8 * s);
 #pragma unroll
-      for (int s = 0; s < S; ++s) {
-        u8v bp[BP];
-#pragma unroll
-        for (int p = 0; p < BP; ++p) bp[p] = *reinterpret_cast<const u8v *>(brow + p * N * RS + 8 * s);
-        // smallest terms first
-        if constexpr (BP == 3) {
-          acc = mfma<T::kF16>(bp[2], A[0][s], acc);
-          if (any_rest) {
-            acc = mfma<T::kF16>(bp[1], A[1][s], acc);
-            acc = mfma<T::kF16>(bp[0], A[2][s], acc);
-          }
-          acc = mfma<T::kF16>(bp[1], A[0][s], acc);
-          if (any_rest) acc = mfma<T::kF16>(bp[0], A[1][s], acc);
-        } else if constexpr (BP == 2) {
-          if (any_rest) acc = mfma<T::kF16>(bp[0], A[1][s], acc);
-          acc = mfma<T::kF16>(bp[1], A[0][s], acc);
+        for (int j = 0; j < 4; ++j) {
+          sy[j] = (uint8_t)(u.x >> (8 * j));
+          sy[4 + j] = (uint8_t)(u.y >> (8 * j));
         }
-        acc = mfma<T::kF16>(bp[0], A[0][s], acc);
+      } else {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          const int64_t si = sbase + 8 * s + j;
+          sy[j] = (valid > 0 && k0 + j < E && si < b.n_symbols) ? symbols[si] : (uint8_t)128;
+        }
       }
-      // lane holds rows n = t*32 + 8*q + 4*h + (0..3) of column w = col
-      if (valid > 0) {
+      u8v a[AP];
+      const bool r = dequant8<PREC>(sy, k0, E, valid > 0, Rb + book * E, Tv + book * n_rows * 256,
+                                    Tz + book * n_rows * 256, gamma != nullptr, gz0, gz1, gz2, a);
+      const bool any_rest = AP > 1 && __any(r);
+      mfma_step<PREC, NT>(acc, a, Bs + col * RS + k0, 32 * RS, N * RS, any_rest);
+    }
+    // lane holds rows n = t*32 + 8*q + 4*h + (0..3) of column w = col
+    if (valid > 0) {
+#pragma unroll
+      for (int t = 0; t < NT; ++t)
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           const int n0 = t * 32 + 8 * q + 4 * h;
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
             if (n0 + i < valid) {
-              const float v = acc[4 * q + i] * oscale;
+              const float v = acc[t][4 * q + i] * oscale;
               if (staged) stage[obase - A0 + n0 + i + m] = v;
               else out[obase + n0 + i] = v;
             }
           }
         }
-      }
     }
     if (staged) {
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");

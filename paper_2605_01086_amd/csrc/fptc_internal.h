@@ -17,11 +17,27 @@ constexpr int kMaxRows = 4;
 constexpr int kMaxLmax = 12;
 constexpr int kTileWindows = 32;  // windows per MFMA tile (one 32x32 output block per wave)
 
+// Everything a wavefront needs to decode one chunk, written by the plan.
+struct ChunkMeta {
+  int64_t first_word;  // global index of the first word holding a symbol of the chunk; -1 = skip
+  int64_t word_end;    // end of the stream's words
+  int64_t sym_base;    // global index of the chunk's first decoded symbol
+  int64_t out_base;    // global index of the chunk's first output sample
+  int32_t first_sym;   // chunk-relative index of the first word's first symbol (<= 0)
+  int32_t n_windows;   // windows in the chunk
+  int32_t out_len;     // output samples of the chunk
+  int32_t stream;
+  int32_t book;
+  int32_t pad[3];
+};
+static_assert(sizeof(ChunkMeta) == 64, "ChunkMeta is one 64-byte record");
+
 // Resolved launch shape (defaults applied, validated).
 struct Shape {
   int wpc;     // windows per chunk
   int waves;   // waves per block
   int blocks;  // persistent grid size (0 = launcher decides)
+  bool auto_waves;  // waves_per_block was 0: each call may pick its own
 };
 
 // Workspace layout of a plan.  Every section starts on a 256-byte boundary.
@@ -32,8 +48,9 @@ struct Shape {
 //   chunk_wsym int64[cap]   in-stream index of that word's first symbol
 //   bwd_part   double[cap*3] backward partial sums per chunk and zone
 //   tile_stream int32[tcap] stream owning the first window of each 32-window tile
+//   chunk_meta ChunkMeta[cap] per-chunk decode record
 struct Layout {
-  size_t hdr, win_off, chunk_off, chunk_word, chunk_wsym, bwd_part, tile_stream, total;
+  size_t hdr, win_off, chunk_off, chunk_word, chunk_wsym, bwd_part, tile_stream, chunk_meta, total;
   int64_t chunk_cap, tile_cap;
 };
 
@@ -48,6 +65,7 @@ struct Plan {
   int64_t *chunk_wsym;
   double *bwd_part;
   int32_t *tile_stream;
+  ChunkMeta *chunk_meta;
   int64_t chunk_cap, tile_cap;
 };
 
@@ -64,6 +82,10 @@ int launch_dqidct(const fptc_batch &b, const fptc_codec &c, const Shape &s, cons
 bool mfma_supported(int N, int E, int precision);
 int launch_dqidct_mfma(const fptc_batch &b, const fptc_codec &c, const Shape &s, const Plan &p,
                        const uint8_t *symbols, const float *gamma, int precision, float *out, void *stream);
+
+bool fused_supported(int N, int E, int precision, int wpc, int waves, int n_books, int n_rows, int lmax);
+int launch_fused(const fptc_batch &b, const fptc_codec &c, const Shape &s, const Plan &p, const float *gamma,
+                 int precision, float *out, int32_t *status, void *stream);
 
 int device_cu_count();
 

@@ -96,7 +96,7 @@ __global__ void __launch_bounds__(kScanThreads) k_plan_chunks(fptc_batch b, int 
                                                               const int64_t *win_off, const int64_t *chunk_off,
                                                               int64_t *chunk_word, int64_t *chunk_wsym,
                                                               int32_t *tile_stream, int64_t tile_cap,
-                                                              int32_t *status) {
+                                                              ChunkMeta *meta, int32_t *status) {
   __shared__ int64_t lds[kScanThreads / kWave + 1];
   const int s = blockIdx.x;
   // Every stream, valid or not, records itself as the owner of the 32-window
@@ -108,11 +108,32 @@ __global__ void __launch_bounds__(kScanThreads) k_plan_chunks(fptc_batch b, int 
   }
   const int64_t c0 = chunk_off[s], nc = chunk_off[s + 1] - c0;
   if (nc <= 0) return;  // empty stream or bad header (then status already flagged)
-  for (int64_t i = threadIdx.x; i < nc; i += kScanThreads) chunk_word[c0 + i] = -1;
-  __syncthreads();
   const int64_t w0 = b.word_off[s], w1 = b.word_off[s + 1];
   const int64_t nw = win_off[s + 1] - win_off[s];
   const int64_t cb = (int64_t)wpc * E;  // symbols per chunk
+  {
+    const int64_t so = b.sample_off[s], L = b.sample_off[s + 1] - so;
+    const int bk = b.book_id ? (int)b.book_id[s] : 0;
+    for (int64_t i = threadIdx.x; i < nc; i += kScanThreads) {
+      chunk_word[c0 + i] = -1;
+      ChunkMeta cm;
+      const int64_t wb = i * wpc;
+      const int64_t nwc = nw - wb < wpc ? nw - wb : wpc;
+      const int64_t ol = L - wb * N < nwc * N ? L - wb * N : nwc * N;
+      cm.first_word = -1;
+      cm.word_end = w1;
+      cm.sym_base = win_off[s] * E + wb * E;
+      cm.out_base = so + wb * N;
+      cm.first_sym = 0;
+      cm.n_windows = (int32_t)nwc;
+      cm.out_len = (int32_t)ol;
+      cm.stream = s;
+      cm.book = bk;
+      cm.pad[0] = cm.pad[1] = cm.pad[2] = 0;
+      meta[c0 + i] = cm;
+    }
+  }
+  __syncthreads();
   int64_t carry = 0;
   int bad = 0;
   for (int64_t base = w0; base < w1; base += (int64_t)kScanThreads * kWordsPerThread) {
@@ -142,6 +163,8 @@ __global__ void __launch_bounds__(kScanThreads) k_plan_chunks(fptc_batch b, int 
         for (; m * cb < p + c && m < nc; ++m) {
           chunk_word[c0 + m] = wb + j;
           chunk_wsym[c0 + m] = p;
+          meta[c0 + m].first_word = wb + j;
+          meta[c0 + m].first_sym = (int32_t)(p - m * cb);
         }
       }
       p += c;
@@ -161,7 +184,7 @@ int launch_plan(const fptc_batch &b, const fptc_codec &c, const Shape &s, const 
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return (int)e;
   hipLaunchKernelGGL(k_plan_chunks, dim3(b.n_streams), dim3(kScanThreads), 0, st, b, c.N, c.E, s.wpc, p.win_off,
-                     p.chunk_off, p.chunk_word, p.chunk_wsym, p.tile_stream, p.tile_cap, status);
+                     p.chunk_off, p.chunk_word, p.chunk_wsym, p.tile_stream, p.tile_cap, p.chunk_meta, status);
   return (int)hipGetLastError();
 }
 

@@ -61,6 +61,8 @@ _SIGS = {
                                            _vp, _vp, _vp]),
     "fptc_dequant_idct": (ctypes.c_int32, [_P(fptc_batch), _P(fptc_codec), _P(fptc_launch), _vp, ctypes.c_size_t,
                                            _vp, _vp, ctypes.c_int32, _vp, _vp]),
+    "fptc_decompress_batch": (ctypes.c_int32, [_P(fptc_batch), _P(fptc_codec), _P(fptc_launch), _vp,
+                                               ctypes.c_size_t, _vp, ctypes.c_int32, _vp, _vp, _vp]),
     "fptc_build_lut": (ctypes.c_int32, [_vp, ctypes.c_int32, _vp]),
     "fptc_canonical_codes": (ctypes.c_int32, [_vp, _vp]),
     "fptc_code_lengths": (ctypes.c_int32, [_vp, ctypes.c_int32, _vp]),
@@ -163,6 +165,16 @@ def fptc_dequant_idct(batch, codec, launch, ws, symbols, gamma, precision, out, 
                                                          ctypes.byref(launch), _ptr(ws),
                                                          ws.numel() * ws.element_size(), _ptr(symbols), _ptr(gamma),
                                                          int(precision), _ptr(out), _stream(stream)))
+
+
+def fptc_decompress_batch(batch, codec, launch, ws, gamma, precision, out, status, stream=None):
+    if isinstance(precision, str):
+        precision = PRECISIONS[precision]
+    _check("fptc_decompress_batch", load().fptc_decompress_batch(ctypes.byref(batch), ctypes.byref(codec),
+                                                                 ctypes.byref(launch), _ptr(ws),
+                                                                 ws.numel() * ws.element_size(), _ptr(gamma),
+                                                                 int(precision), _ptr(out), _ptr(status),
+                                                                 _stream(stream)))
 
 
 # ------------------------------------------------------------ host calls

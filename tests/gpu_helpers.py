@@ -19,7 +19,7 @@ def qparams(p):
 
 
 def run_gpu(case: Case, launch=None, precision="fp32", use_gamma=True, words_override=None, symlen_override=None,
-            repeat=1):
+            repeat=1, fused=False):
     import torch
     from paper_2605_01086_amd import codec as C
     from paper_2605_01086_amd import fptc as F
@@ -44,11 +44,16 @@ def run_gpu(case: Case, launch=None, precision="fp32", use_gamma=True, words_ove
     results = []
     for _ in range(repeat):
         F.fptc_plan_batch(batch.c, codec.c, lc, ws, status)
-        F.fptc_decode_batch(batch.c, codec.c, lc, ws, sym, status)
-        F.fptc_dequant_idct(batch.c, codec.c, lc, ws, sym, gamma, precision, out)
+        if fused:
+            F.fptc_decompress_batch(batch.c, codec.c, lc, ws, gamma, precision, out, status)
+        else:
+            F.fptc_decode_batch(batch.c, codec.c, lc, ws, sym, status)
+            F.fptc_dequant_idct(batch.c, codec.c, lc, ws, sym, gamma, precision, out)
         torch.cuda.synchronize()
         results.append((sym.cpu().numpy().copy(), out.cpu().numpy().copy(), status.cpu().numpy().copy()))
     s_h, o_h, st_h = results[-1]
+    if fused:
+        assert np.all(s_h == SENT_U8), "the fused path must not touch the symbol array"
     assert np.all(s_h[batch.n_symbols:] == SENT_U8), "decode wrote past the symbol array"
     assert np.all(o_h[batch.n_samples:] == SENT_F32), "dequant+IDCT wrote past the output array"
     return dict(sym=s_h[:batch.n_symbols], out=o_h[:batch.n_samples], status=st_h, batch=batch, runs=results)
@@ -81,7 +86,7 @@ def _diagnose(case: Case, res, bad_stream: int) -> str:
     return "\n".join(lines)
 
 
-def check_parity(case: Case, res, tol=1e-5, skip=()):
+def check_parity(case: Case, res, tol=1e-5, skip=(), check_symbols=True):
     batch = res["batch"]
     worst = 0.0
     for i in range(len(case.signals)):
@@ -90,7 +95,9 @@ def check_parity(case: Case, res, tol=1e-5, skip=()):
         assert res["status"][i] == 0, (i, res["status"][i])
         s0, s1 = batch.sym_off_h[i], batch.sym_off_h[i + 1]
         got = res["sym"][s0:s1]
-        assert np.array_equal(got, case.symbols[i]), f"stream {i}: symbols differ at {np.flatnonzero(got != case.symbols[i])[:8]}"
+        if check_symbols:
+            assert np.array_equal(got, case.symbols[i]), \
+                f"stream {i}: symbols differ at {np.flatnonzero(got != case.symbols[i])[:8]}"
         o0, o1 = batch.sample_off_h[i], batch.sample_off_h[i + 1]
         err = range_rel_err(res["out"][o0:o1], case.recon[i])
         worst = max(worst, err)
