@@ -39,10 +39,7 @@ int resolve_shape(const fptc_launch *l, const fptc_codec *c, Shape *s) {
   s->auto_waves = !(l && l->waves_per_block);
   s->blocks = l ? l->blocks : 0;
   if (s->wpc < 1 || s->wpc > 1024 || s->waves < 1 || s->waves > 16 || s->blocks < 0) return FPTC_ERR_INVALID_ARG;
-  // LDS budget of the decode kernel: lookup tables + one symbol buffer per wave.
-  size_t lut = ((size_t)(c->n_books << c->lmax) * 2 + 15) & ~(size_t)15;
-  size_t buf = (((size_t)s->wpc * c->E + 16) + 15) & ~(size_t)15;
-  if (lut + s->waves * buf > 64 * 1024) return FPTC_ERR_UNSUPPORTED;
+  (void)c;
   return FPTC_OK;
 }
 
@@ -62,10 +59,6 @@ Layout layout_for(const fptc_batch *b, const fptc_codec *c, const Shape &s) {
   off = align256(off + (n + 1) * sizeof(int64_t));
   L.chunk_off = off;
   off = align256(off + (n + 1) * sizeof(int64_t));
-  L.chunk_word = off;
-  off = align256(off + L.chunk_cap * sizeof(int64_t));
-  L.chunk_wsym = off;
-  off = align256(off + L.chunk_cap * sizeof(int64_t));
   L.bwd_part = off;
   off = align256(off + L.chunk_cap * 3 * sizeof(double));
   L.tile_cap = (max_windows + kTileWindows - 1) / kTileWindows + 1;
@@ -83,8 +76,6 @@ Plan plan_view(void *ws, const Layout &L) {
   v.hdr = reinterpret_cast<int64_t *>(p + L.hdr);
   v.win_off = reinterpret_cast<int64_t *>(p + L.win_off);
   v.chunk_off = reinterpret_cast<int64_t *>(p + L.chunk_off);
-  v.chunk_word = reinterpret_cast<int64_t *>(p + L.chunk_word);
-  v.chunk_wsym = reinterpret_cast<int64_t *>(p + L.chunk_wsym);
   v.bwd_part = reinterpret_cast<double *>(p + L.bwd_part);
   v.tile_stream = reinterpret_cast<int32_t *>(p + L.tile_stream);
   v.chunk_meta = reinterpret_cast<ChunkMeta *>(p + L.chunk_meta);
@@ -139,6 +130,7 @@ int32_t fptc_decode_batch(const fptc_batch *batch, const fptc_codec *codec, cons
   int rc;
   if ((rc = check_batch(batch)) || (rc = check_codec(codec)) || (rc = resolve_shape(launch, codec, &s))) return rc;
   if (!ws || (!symbols_out && batch->n_symbols > 0)) return FPTC_ERR_INVALID_ARG;
+  if (decode_lds_bytes(*codec, s) > 160 * 1024) return FPTC_ERR_UNSUPPORTED;
   Layout L = layout_for(batch, codec, s);
   if (ws_bytes < L.total) return FPTC_ERR_WORKSPACE;
   return status_of(
@@ -170,8 +162,8 @@ int32_t fptc_decompress_batch(const fptc_batch *batch, const fptc_codec *codec, 
   if ((rc = check_batch(batch)) || (rc = check_codec(codec)) || (rc = resolve_shape(launch, codec, &s))) return rc;
   if (!ws || (!out && batch->n_samples > 0)) return FPTC_ERR_INVALID_ARG;
   if (precision < FPTC_FP32_SIMT || precision > FPTC_BF16X3) return FPTC_ERR_INVALID_ARG;
-  if (s.auto_waves) {  // the most waves (up to 12) whose LDS fits
-    s.waves = 12;
+  if (s.auto_waves) {  // the most waves (up to 16) whose LDS fits
+    s.waves = 16;
     while (s.waves > 1 && !fused_supported(codec->N, codec->E, precision, s.wpc, s.waves, codec->n_books, codec->n_rows, codec->lmax))
       --s.waves;
   }

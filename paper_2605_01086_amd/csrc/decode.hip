@@ -19,7 +19,7 @@
 namespace fptc {
 namespace {
 
-__global__ void k_decode(const uint64_t *__restrict__ words, const uint8_t *__restrict__ symlen, int n_streams,
+__global__ void __launch_bounds__(1024) k_decode(const uint64_t *__restrict__ words, const uint8_t *__restrict__ symlen, int n_streams,
                          int64_t n_symbols, int E, int lmax, int n_books, int wpc, const uint16_t *lut_g,
                          const int64_t *hdr, const ChunkMeta *__restrict__ meta, uint8_t *symbols, int32_t *status) {
   extern __shared__ __align__(16) unsigned char lds[];
@@ -72,13 +72,25 @@ __global__ void k_decode(const uint64_t *__restrict__ words, const uint8_t *__re
 
 }  // namespace
 
+size_t decode_lds_bytes(const fptc_codec &c, const Shape &s) {
+  const size_t lut_bytes = (((size_t)(c.n_books << c.lmax) * 2) + 15) & ~(size_t)15;
+  const size_t buf_bytes = (((size_t)s.wpc * c.E + 16) + 15) & ~(size_t)15;
+  return lut_bytes + (size_t)s.waves * buf_bytes;
+}
+
 int launch_decode(const fptc_batch &b, const fptc_codec &c, const Shape &s, const Plan &p, uint8_t *symbols,
                   int32_t *status, void *stream) {
   const int threads = s.waves * kWave;
-  const int lut_bytes = (((c.n_books << c.lmax) * 2) + 15) & ~15;
-  const int buf_bytes = ((s.wpc * c.E + 16) + 15) & ~15;
-  const size_t lds = (size_t)lut_bytes + (size_t)s.waves * buf_bytes;
-  int blocks = s.blocks > 0 ? s.blocks : device_cu_count() * 8;
+  const size_t lds = decode_lds_bytes(c, s);
+  static bool attr_set = false;
+  if (!attr_set) {
+    if (hipFuncSetAttribute(reinterpret_cast<const void *>(k_decode), hipFuncAttributeMaxDynamicSharedMemorySize,
+                            160 * 1024) != hipSuccess)
+      return (int)hipErrorInvalidValue;
+    attr_set = true;
+  }
+  const int per_cu = (int)((160 * 1024) / lds);
+  int blocks = s.blocks > 0 ? s.blocks : device_cu_count() * (per_cu < 1 ? 1 : (per_cu > 8 ? 8 : per_cu));
   hipLaunchKernelGGL(k_decode, dim3(blocks), dim3(threads), lds, (hipStream_t)stream, b.words, b.symlen, b.n_streams,
                      b.n_symbols, c.E, c.lmax, c.n_books, s.wpc, c.lut, p.hdr, p.chunk_meta, symbols, status);
   return (int)hipGetLastError();

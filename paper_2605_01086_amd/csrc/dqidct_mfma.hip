@@ -6,7 +6,7 @@
 // i.e. the transposed product basis^T x coefficients^T, with
 // v_mfma_f32_32x32x16_{f16,bf16}: FP32 accumulation, 16-bit operands.  The
 // transposed form leaves each lane holding four consecutive samples of one
-// window, so the result leaves as 16-byte stores.
+// window, so the result leaves as 16-byte stores straight from registers.
 //
 // Bins are mapped to MFMA k-slots so that each lane's coefficients are one
 // contiguous run of symbols: lane half h owns bins [h*Kp/2, (h+1)*Kp/2), k-step
@@ -31,20 +31,13 @@ namespace {
 
 constexpr int kThreads = 256;
 
-// LDS bytes of one instantiation: basis pieces, tables, per-wave staging.
-__host__ __device__ constexpr size_t mfma_lds_bytes(int bpieces, int N, int Kp, int n_books, int n_rows, int E,
-                                                    bool stage) {
-  return (size_t)bpieces * N * (Kp + 8) * 2 + (size_t)n_books * n_rows * 256 * 5 + (size_t)n_books * E + 16 +
-         (stage ? (size_t)(kThreads / 64) * (kTileWindows * N + 4) * 4 : 0);
+// LDS bytes of one instantiation: basis pieces and tables.
+__host__ __device__ constexpr size_t mfma_lds_bytes(int bpieces, int N, int Kp, int n_books, int n_rows, int E) {
+  return (size_t)bpieces * N * (Kp + 8) * 2 + (size_t)n_books * n_rows * 256 * 5 + (size_t)n_books * E + 16;
 }
 
-// Whether an instantiation stages its outputs (decided for the largest tables).
-template <int PREC, int S, int NT>
-constexpr bool kStage = mfma_lds_bytes(Traits<PREC>::kBPieces, NT * 32, S * 16, kMaxBooks, kMaxRows, S * 16, true) <=
-                        160 * 1024;
-
 // S = Kp / 16 k-steps (Kp = E rounded up to 16), NT = N / 32 output row tiles.
-template <int PREC, int S, int NT, bool STAGE>
+template <int PREC, int S, int NT>
 __global__ void __launch_bounds__(kThreads) k_dqidct_mfma(fptc_batch b, int E, int n_books, int n_rows,
                                                           const float *deq_val, const uint8_t *deq_zone,
                                                           const uint8_t *row_of_bin, const float *basis,
@@ -109,21 +102,6 @@ __global__ void __launch_bounds__(kThreads) k_dqidct_mfma(fptc_batch b, int E, i
         gz2 = gamma[3 * (int64_t)s + 2];
       }
     }
-    // ---- output placement.  Windows are stored in global order with their
-    // padding dropped, so a tile's valid samples normally form one contiguous
-    // run [A0, A0 + R): stage them in LDS by output address and store the run
-    // on the destination's 16-byte grid.  A tile that is not contiguous (only
-    // possible with corrupt headers) is stored element by element.
-    const int64_t oend = obase + valid;
-    const int64_t prev_end = __shfl(oend, (col + 31) & 31 | (h << 5), 64);
-    const int prev_valid = __shfl(valid, (col + 31) & 31 | (h << 5), 64);
-    const bool link_ok = valid == 0 || col == 0 || (prev_valid > 0 && obase == prev_end);
-    const bool staged = STAGE && __all(link_ok);
-    const int64_t A0 = __shfl(obase, 0, 64);
-    const int m = (int)((reinterpret_cast<uintptr_t>(out + A0) >> 2) & 3);
-    float *stage = reinterpret_cast<float *>(Rb + n_books * E + 15 - ((uintptr_t)(Rb + n_books * E + 15) & 15)) +
-                   (size_t)wid * (kTileWindows * N + 4);
-
     // ---- contraction, one k-step at a time from the highest bins down
     f16v acc[NT];
 #pragma unroll
@@ -155,48 +133,10 @@ __global__ void __launch_bounds__(kThreads) k_dqidct_mfma(fptc_batch b, int E, i
       const bool any_rest = AP > 1 && __any(r);
       mfma_step<PREC, NT>(acc, a, Bs + col * RS + k0, 32 * RS, N * RS, any_rest);
     }
-    // lane holds rows n = t*32 + 8*q + 4*h + (0..3) of column w = col
+    // lane holds rows n = t*32 + 8*q + 4*h + (0..3) of its window
     if (valid > 0) {
 #pragma unroll
-      for (int t = 0; t < NT; ++t)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int n0 = t * 32 + 8 * q + 4 * h;
-#pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            if (n0 + i < valid) {
-              const float v = acc[t][4 * q + i] * oscale;
-              if (staged) stage[obase - A0 + n0 + i + m] = v;
-              else out[obase + n0 + i] = v;
-            }
-          }
-        }
-    }
-    if (staged) {
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      // run length: end of the last window with samples
-      int last = 31;
-      const uint64_t has = __ballot(valid > 0);
-      last = has ? 63 - __builtin_clzll(has & 0xffffffffull) : -1;
-      if (last >= 0) {
-        const int64_t R = __shfl(oend, last, 64) - A0;
-        float *dst = out + A0 - m;  // 16-byte aligned
-        const int nblk = (int)((m + R + 3) >> 2);
-        for (int k = lane; k < nblk; k += 64) {
-          const int lo = 4 * k;
-          if (lo >= m && lo + 4 <= m + R) {
-            *reinterpret_cast<float4 *>(dst + lo) = *reinterpret_cast<const float4 *>(stage + lo);
-          } else {
-            for (int j = lo; j < lo + 4; ++j)
-              if (j >= m && j < m + R) dst[j] = stage[j];
-          }
-        }
-      }
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      for (int t = 0; t < NT; ++t) store_block(out + obase, acc[t], t * 32, h, valid, oscale);
     }
   }
 }
@@ -205,9 +145,8 @@ template <int PREC, int S, int NT>
 int launch_t(const fptc_batch &b, const fptc_codec &c, const Shape &sh, const Plan &p, const uint8_t *symbols,
              const float *gamma, float *out, void *stream) {
   constexpr int N = NT * 32, Kp = S * 16;
-  constexpr bool stage = kStage<PREC, S, NT>;
-  const size_t lds = mfma_lds_bytes(Traits<PREC>::kBPieces, N, Kp, c.n_books, c.n_rows, c.E, stage);
-  auto kern = k_dqidct_mfma<PREC, S, NT, stage>;
+  const size_t lds = mfma_lds_bytes(Traits<PREC>::kBPieces, N, Kp, c.n_books, c.n_rows, c.E);
+  auto kern = k_dqidct_mfma<PREC, S, NT>;
   static bool attr_set = false;  // one attribute call per instantiation
   if (!attr_set) {
     if (hipFuncSetAttribute(reinterpret_cast<const void *>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -215,7 +154,8 @@ int launch_t(const fptc_batch &b, const fptc_codec &c, const Shape &sh, const Pl
       return (int)hipErrorInvalidValue;
     attr_set = true;
   }
-  int blocks = sh.blocks > 0 ? sh.blocks : device_cu_count() * 2;
+  const int per_cu = (int)((160 * 1024) / lds);
+  int blocks = sh.blocks > 0 ? sh.blocks : device_cu_count() * (per_cu < 1 ? 1 : (per_cu > 8 ? 8 : per_cu));
   hipLaunchKernelGGL(kern, dim3(blocks), dim3(kThreads), lds, (hipStream_t)stream, b, c.E, c.n_books, c.n_rows,
                      c.deq_val, c.deq_zone, c.row_of_bin, c.basis, p.hdr, p.win_off, p.tile_stream, symbols, gamma,
                      out);
@@ -245,7 +185,7 @@ bool mfma_supported(int N, int E, int precision) {
   // LDS: basis pieces + tables must fit in 160 KB (staging is optional)
   const int Kp = (E + 15) / 16 * 16;
   const int pieces = precision == FPTC_BF16X3 ? 3 : (precision == FPTC_FP16X2 ? 2 : 1);
-  return mfma_lds_bytes(pieces, N, Kp, kMaxBooks, kMaxRows, E, false) <= 160 * 1024;
+  return mfma_lds_bytes(pieces, N, Kp, kMaxBooks, kMaxRows, E) <= 160 * 1024;
 }
 
 int launch_dqidct_mfma(const fptc_batch &b, const fptc_codec &c, const Shape &s, const Plan &p,

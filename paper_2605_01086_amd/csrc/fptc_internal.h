@@ -44,13 +44,11 @@ struct Shape {
 //   hdr        int64[8]     [0] = chunk count, [1] = window count
 //   win_off    int64[n+1]   exclusive prefix of ceil(L_s / N)
 //   chunk_off  int64[n+1]   exclusive prefix of ceil(n_win_s / wpc) (0 for bad headers)
-//   chunk_word int64[cap]   global index of the first word holding a symbol of the chunk, -1 if none
-//   chunk_wsym int64[cap]   in-stream index of that word's first symbol
 //   bwd_part   double[cap*3] backward partial sums per chunk and zone
 //   tile_stream int32[tcap] stream owning the first window of each 32-window tile
 //   chunk_meta ChunkMeta[cap] per-chunk decode record
 struct Layout {
-  size_t hdr, win_off, chunk_off, chunk_word, chunk_wsym, bwd_part, tile_stream, chunk_meta, total;
+  size_t hdr, win_off, chunk_off, bwd_part, tile_stream, chunk_meta, total;
   int64_t chunk_cap, tile_cap;
 };
 
@@ -61,8 +59,6 @@ struct Plan {
   int64_t *hdr;
   int64_t *win_off;
   int64_t *chunk_off;
-  int64_t *chunk_word;
-  int64_t *chunk_wsym;
   double *bwd_part;
   int32_t *tile_stream;
   ChunkMeta *chunk_meta;
@@ -74,6 +70,7 @@ Plan plan_view(void *ws, const Layout &L);
 // Kernel launchers (return hipError_t as int).
 int launch_plan(const fptc_batch &b, const fptc_codec &c, const Shape &s, const Plan &p, int32_t *status,
                 void *stream);
+size_t decode_lds_bytes(const fptc_codec &c, const Shape &s);
 int launch_decode(const fptc_batch &b, const fptc_codec &c, const Shape &s, const Plan &p, uint8_t *symbols,
                   int32_t *status, void *stream);
 int launch_dqidct(const fptc_batch &b, const fptc_codec &c, const Shape &s, const Plan &p,

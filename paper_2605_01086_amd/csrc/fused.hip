@@ -12,9 +12,8 @@
 //     current ones decode.
 //  2. per 32 windows: dequantize from LDS into split 16-bit operands, contract
 //     with the split IDCT basis on v_mfma_f32_32x32x16 (exactly the arithmetic
-//     of the stand-alone MFMA kernel, so results are bit-identical), stage the
-//     32-window output -- one contiguous run, all windows belong to the chunk's
-//     stream -- in LDS and store it on the 16-byte grid.
+//     of the stand-alone MFMA kernel, so results are bit-identical) and store
+//     each lane's four consecutive samples with one 16-byte write.
 #include <hip/hip_runtime.h>
 
 #include "fptc_internal.h"
@@ -26,15 +25,13 @@ namespace {
 
 __host__ __device__ constexpr size_t align16(size_t x) { return (x + 15) & ~(size_t)15; }
 
-constexpr int kMaxFusedWaves = 12;
+constexpr int kMaxFusedWaves = 16;
 constexpr int kMaxFusedThreads = kMaxFusedWaves * 64;
 
-// Per-wave LDS region: the chunk's symbols, then (unless it can reuse the
-// symbol buffer, i.e. one tile per chunk) the output staging buffer.
+// Per-wave LDS region: the chunk's decoded symbols.
 __host__ __device__ inline size_t fused_wave_bytes(int N, int E, int wpc) {
-  const size_t sym = align16((size_t)wpc * E + 16);
-  const size_t stage = align16((size_t)(kTileWindows * N + 4) * 4);
-  return wpc <= kTileWindows ? (sym > stage ? sym : stage) : sym + stage;
+  (void)N;
+  return align16((size_t)wpc * E + 16);
 }
 
 __host__ __device__ inline size_t fused_lds_bytes(int bpieces, int N, int E, int Kp, int wpc, int waves, int n_books,
@@ -82,7 +79,6 @@ __global__ void __launch_bounds__(kMaxFusedThreads) k_fused(const uint64_t *__re
   const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63, col = lane & 31, h = lane >> 5;
   unsigned char *sb = wave_base + (size_t)wid * fused_wave_bytes(N, E, wpc);
-  float *stage = reinterpret_cast<float *>(wpc <= kTileWindows ? sb : sb + align16((size_t)wpc * E + 16));
   const int hs = 32 - lmax;  // peek = top lmax bits of the word = hi32 >> hs
   const float oscale = 1.0f / (T::kF16 ? kBasisScaleF16 : 1.0f);
   const bool e_vec = (E % 16) == 0;
@@ -107,7 +103,7 @@ __global__ void __launch_bounds__(kMaxFusedThreads) k_fused(const uint64_t *__re
     if (err && status) atomicOr(&status[s], err);
     wave_sync_lds();
 
-    // ---- 2. per 32 windows: dequantize, contract, stage, store
+    // ---- 2. per 32 windows: dequantize, contract, store
     for (int tt = 0; tt * kTileWindows < w_cnt; ++tt) {
       const int wr = tt * kTileWindows + col;  // chunk-relative window of this lane's column
       const int valid = wr < w_cnt ? min(N, cm.out_len - wr * N) : 0;
@@ -139,36 +135,13 @@ __global__ void __launch_bounds__(kMaxFusedThreads) k_fused(const uint64_t *__re
         const bool any_rest = AP > 1 && __any(r);
         mfma_step<PREC, NT>(acc, a, Bs + col * RS + k0, 32 * RS, N * RS, any_rest);
       }
-      // The staging buffer may overlay the symbols (one tile per chunk): all
-      // symbol reads of the wave are complete once the operands are built.
-      wave_sync_lds();
-      const int64_t A0 = cm.out_base + (int64_t)tt * kTileWindows * N;
-      const int mis = (int)((reinterpret_cast<uintptr_t>(out + A0) >> 2) & 3);
-      // Unconditional: slots of samples past the stream's end, or of windows
-      // past the chunk, lie outside the run that is stored.
+      // this lane's window starts at out_base + wr * N; all windows of a chunk
+      // are consecutive in one stream
+      if (valid > 0) {
+        float *dst = out + cm.out_base + (int64_t)wr * N;
 #pragma unroll
-      for (int t = 0; t < NT; ++t)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int n0 = t * 32 + 8 * q + 4 * h;
-#pragma unroll
-          for (int i = 0; i < 4; ++i) stage[col * N + n0 + i + mis] = acc[t][4 * q + i] * oscale;
-        }
-      wave_sync_lds();
-      // contiguous run [A0, A0 + R) of this tile's samples
-      const int R = min(cm.out_len - tt * kTileWindows * N, kTileWindows * N);
-      float *dst = out + A0 - mis;
-      const int nblk = (mis + R + 3) >> 2;
-      for (int k = lane; k < nblk; k += 64) {
-        const int lo = 4 * k;
-        if (lo >= mis && lo + 4 <= mis + R) {
-          *reinterpret_cast<float4 *>(dst + lo) = *reinterpret_cast<const float4 *>(stage + lo);
-        } else {
-          for (int j = lo; j < lo + 4; ++j)
-            if (j >= mis && j < mis + R) dst[j] = stage[j];
-        }
+        for (int t = 0; t < NT; ++t) store_block(dst, acc[t], t * 32, h, valid, oscale);
       }
-      wave_sync_lds();
     }
   }
 }

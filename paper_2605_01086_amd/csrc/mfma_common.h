@@ -150,6 +150,27 @@ __device__ inline void stage_basis(uint16_t *Bs, const float *basis, int N, int 
   }
 }
 
+typedef float f4u __attribute__((ext_vector_type(4), aligned(4)));  // 16 bytes, 4-byte aligned
+
+// Store this lane's results of one 32x32 output block: rows n = nbase + 8 q +
+// 4 h + (0..3) of its window, whose samples start at dst; only the first
+// `valid` samples of the window exist.  Four consecutive samples leave as one
+// 16-byte store (global memory takes them at 4-byte alignment on gfx950).
+__device__ inline void store_block(float *dst, const f16v &acc, int nbase, int h, int valid, float scale) {
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int n0 = nbase + 8 * q + 4 * h;
+    const f4u v = {acc[4 * q] * scale, acc[4 * q + 1] * scale, acc[4 * q + 2] * scale, acc[4 * q + 3] * scale};
+    if (n0 + 4 <= valid) {
+      *reinterpret_cast<f4u *>(dst + n0) = v;
+    } else {
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        if (n0 + i < valid) dst[n0 + i] = v[i];
+    }
+  }
+}
+
 // Inclusive prefix sum across a 64-lane wavefront with DPP row shifts and row
 // broadcasts (no LDS round trips).
 __device__ inline int wave_incl_scan_dpp(int x) {

@@ -7,13 +7,14 @@
 #include <hip/hip_runtime.h>
 
 #include "fptc_internal.h"
+#include "mfma_common.h"
 
 namespace fptc {
 namespace {
 
 constexpr int kPlanThreads = 1024;
 constexpr int kScanThreads = 256;
-constexpr int kWordsPerThread = 4;
+constexpr int kWordsPerThread = 16;  // one 16-byte symlen load per thread and iteration
 
 // Inclusive scan across one 64-lane wavefront.
 template <typename T>
@@ -88,16 +89,37 @@ __global__ void __launch_bounds__(kPlanThreads) k_plan_streams(fptc_batch b, int
   }
 }
 
+// Exclusive block scan of int values with DPP wave scans; returns the
+// exclusive prefix and the block total.
+__device__ inline int block_excl_scan_dpp(int v, int *lds, int &total) {
+  const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+  constexpr int NW = kScanThreads / kWave;
+  const int incl = wave_incl_scan_dpp(v);
+  if (lane == kWave - 1) lds[wid] = incl;
+  __syncthreads();
+  int before = 0, tot = 0;
+#pragma unroll
+  for (int i = 0; i < NW; ++i) {
+    const int x = lds[i];
+    before += i < wid ? x : 0;
+    tot += x;
+  }
+  __syncthreads();
+  total = tot;
+  return before + incl - v;
+}
+
 // One workgroup per stream: exclusive scan of the stream's symlen; every word
 // whose symbol range [p, p + symlen) contains the first symbol of a chunk
-// (a multiple of wpc * E) is recorded as that chunk's first word.  Also checks
-// the symbol total and the symlen bound.
+// (a multiple of wpc * E) is recorded in that chunk's record.  Also writes the
+// per-chunk records, the 32-window tile owners, and checks the symbol total
+// and the symlen bound.  4096 words per iteration, 16 per thread, the next
+// iteration's bytes loaded while the current ones are scanned.
 __global__ void __launch_bounds__(kScanThreads) k_plan_chunks(fptc_batch b, int N, int E, int wpc,
                                                               const int64_t *win_off, const int64_t *chunk_off,
-                                                              int64_t *chunk_word, int64_t *chunk_wsym,
                                                               int32_t *tile_stream, int64_t tile_cap,
                                                               ChunkMeta *meta, int32_t *status) {
-  __shared__ int64_t lds[kScanThreads / kWave + 1];
+  __shared__ int lds[kScanThreads / kWave];
   const int s = blockIdx.x;
   // Every stream, valid or not, records itself as the owner of the 32-window
   // tiles whose first window it holds, so a tile's first stream is one load.
@@ -115,7 +137,6 @@ __global__ void __launch_bounds__(kScanThreads) k_plan_chunks(fptc_batch b, int 
     const int64_t so = b.sample_off[s], L = b.sample_off[s + 1] - so;
     const int bk = b.book_id ? (int)b.book_id[s] : 0;
     for (int64_t i = threadIdx.x; i < nc; i += kScanThreads) {
-      chunk_word[c0 + i] = -1;
       ChunkMeta cm;
       const int64_t wb = i * wpc;
       const int64_t nwc = nw - wb < wpc ? nw - wb : wpc;
@@ -134,16 +155,36 @@ __global__ void __launch_bounds__(kScanThreads) k_plan_chunks(fptc_batch b, int 
     }
   }
   __syncthreads();
+
+  // iterate over 16-byte aligned groups of symlen bytes covering [w0, w1)
+  const bool vec = (reinterpret_cast<uintptr_t>(b.symlen) & 15) == 0;
+  const int64_t base0 = vec ? (w0 & ~(int64_t)15) : w0;
+  constexpr int kIter = kScanThreads * kWordsPerThread;
+  auto load16 = [&](int64_t first, uint8_t (&c)[kWordsPerThread]) {
+    if (vec && first >= w0 && first + kWordsPerThread <= w1) {
+      const uint4 u = *reinterpret_cast<const uint4 *>(b.symlen + first);
+      const uint32_t x[4] = {u.x, u.y, u.z, u.w};
+#pragma unroll
+      for (int j = 0; j < kWordsPerThread; ++j) c[j] = (uint8_t)(x[j >> 2] >> (8 * (j & 3)));
+    } else {
+#pragma unroll
+      for (int j = 0; j < kWordsPerThread; ++j) {
+        const int64_t w = first + j;
+        c[j] = (w >= w0 && w < w1) ? b.symlen[w] : (uint8_t)0;
+      }
+    }
+  };
   int64_t carry = 0;
   int bad = 0;
-  for (int64_t base = w0; base < w1; base += (int64_t)kScanThreads * kWordsPerThread) {
+  uint8_t nxt[kWordsPerThread];
+  load16(base0 + (int64_t)threadIdx.x * kWordsPerThread, nxt);
+  for (int64_t base = base0; base < w1; base += kIter) {
     const int64_t wb = base + (int64_t)threadIdx.x * kWordsPerThread;
     int cnt[kWordsPerThread];
     int sum = 0;
 #pragma unroll
     for (int j = 0; j < kWordsPerThread; ++j) {
-      const int64_t w = wb + j;
-      int c = w < w1 ? (int)b.symlen[w] : 0;
+      int c = nxt[j];
       if (c > 64) {
         bad |= FPTC_STREAM_BAD_SYMLEN;
         c = 64;
@@ -151,8 +192,9 @@ __global__ void __launch_bounds__(kScanThreads) k_plan_chunks(fptc_batch b, int 
       cnt[j] = c;
       sum += c;
     }
-    int64_t tot;
-    int64_t p = carry + block_excl_scan<int64_t, kScanThreads>((int64_t)sum, lds, tot);
+    if (base + kIter < w1) load16(wb + kIter, nxt);
+    int tot;
+    int64_t p = carry + block_excl_scan_dpp(sum, lds, tot);
     carry += tot;
 #pragma unroll
     for (int j = 0; j < kWordsPerThread; ++j) {
@@ -161,8 +203,6 @@ __global__ void __launch_bounds__(kScanThreads) k_plan_chunks(fptc_batch b, int 
         // chunk starts m * cb with p <= m * cb < p + c
         int64_t m = (p + cb - 1) / cb;
         for (; m * cb < p + c && m < nc; ++m) {
-          chunk_word[c0 + m] = wb + j;
-          chunk_wsym[c0 + m] = p;
           meta[c0 + m].first_word = wb + j;
           meta[c0 + m].first_sym = (int32_t)(p - m * cb);
         }
@@ -184,7 +224,7 @@ int launch_plan(const fptc_batch &b, const fptc_codec &c, const Shape &s, const 
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return (int)e;
   hipLaunchKernelGGL(k_plan_chunks, dim3(b.n_streams), dim3(kScanThreads), 0, st, b, c.N, c.E, s.wpc, p.win_off,
-                     p.chunk_off, p.chunk_word, p.chunk_wsym, p.tile_stream, p.tile_cap, p.chunk_meta, status);
+                     p.chunk_off, p.tile_stream, p.tile_cap, p.chunk_meta, status);
   return (int)hipGetLastError();
 }
 

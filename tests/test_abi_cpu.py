@@ -158,10 +158,24 @@ def test_argument_errors_return_before_any_launch():
         bb, cc, ll = _fake_structs()
         setattr(ll, field, bad)
         assert F.fptc_workspace_size(bb, cc, ll) == 0
-    # a decode chunk whose symbol buffer cannot fit in LDS is refused
+    # a decode chunk whose symbol buffers cannot fit in LDS is refused before launch
     bb, cc, ll = _fake_structs()
-    cc.N, cc.E, ll.windows_per_chunk = 256, 256, 1024
-    assert F.fptc_workspace_size(bb, cc, ll) == 0
+    bb.n_symbols = 1 << 20
+    cc.N, cc.E, ll.windows_per_chunk, ll.waves_per_block = 256, 256, 1024, 16
+    size = F.fptc_workspace_size(bb, cc, ll)
+    assert size > 0
+    assert lib.fptc_decode_batch(by(bb), by(cc), by(ll), 16, size, 16, 16, None) == F.FPTC_ERR_UNSUPPORTED
+    # the fused path: unsupported precision / window size / LDS budget
+    bb, cc, ll = _fake_structs()
+    size = F.fptc_workspace_size(bb, cc, ll)
+    assert lib.fptc_decompress_batch(by(bb), by(cc), by(ll), 16, size, None, 0, 16, 16, None) == F.FPTC_ERR_UNSUPPORTED
+    cc.N, cc.E = 16, 16
+    size = F.fptc_workspace_size(bb, cc, ll)
+    assert lib.fptc_decompress_batch(by(bb), by(cc), by(ll), 16, size, None, 2, 16, 16, None) == F.FPTC_ERR_UNSUPPORTED
+    cc.N, cc.E, cc.n_books = 128, 128, 8
+    ll.windows_per_chunk, ll.waves_per_block = 1024, 16
+    size = F.fptc_workspace_size(bb, cc, ll)
+    assert lib.fptc_decompress_batch(by(bb), by(cc), by(ll), 16, size, None, 4, 16, 16, None) == F.FPTC_ERR_UNSUPPORTED
 
 
 def test_codec_tables_are_dense_row_major_per_book(O):
