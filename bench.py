@@ -212,7 +212,9 @@ def main():
     ap.add_argument("--path", default="fused", choices=["fused", "split"],
                     help="fused: one decode+dequant+IDCT kernel; split: decode kernel then dequant+IDCT kernel")
     ap.add_argument("--wpc", type=int, default=32)
-    ap.add_argument("--waves", type=int, default=8)
+    ap.add_argument("--waves", type=int, default=0, help="waves per block (0 = library default)")
+    ap.add_argument("--autotune", action="store_true", help="pick the launch shape by timing candidates")
+    ap.add_argument("--graph", action="store_true", help="replay the step as one captured HIP graph")
     ap.add_argument("--blocks", type=int, default=0)
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -239,12 +241,29 @@ def main():
     torch.cuda.set_device(0)
     codec = C.DeviceCodec(lens_tab, q, 12)
     batch = C.DeviceBatch(words, symlen, word_off, sample_off, q.N, q.E, dom if args.workload == "batch" else None)
-    launch = C.Launch(args.wpc, args.waves, args.blocks)
-    dec = C.Decoder(batch, codec, launch)
     fused = args.path == "fused"
     if fused and args.precision == "fp32":
         raise SystemExit("the fused path runs the MFMA precisions (fp16x2, bf16x3, fp16, bf16)")
+    launch = C.Launch(args.wpc, args.waves, args.blocks)
+    tuned = None
+    if args.autotune:
+        from paper_2605_01086_amd import autotune
+        launch, tuned = autotune.tune(batch, codec, args.precision, fused, use_cache=False)
+    dec = C.Decoder(batch, codec, launch)
     ms_step, per_kernel, gpu_steps = time_batched(dec, args.steps, args.warmup, args.precision, fused)
+    graph_ms = None
+    if args.graph:
+        from paper_2605_01086_amd.graph import CapturedStep
+        step = CapturedStep(dec, args.precision, fused)
+        for _ in range(args.warmup):
+            step.replay()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            step.replay()
+        torch.cuda.synchronize()
+        graph_ms = (time.perf_counter() - t0) / args.steps * 1e3
+        ms_step = graph_ms
     status = dec.status.cpu().numpy()
     if np.any(status != 0):
         raise SystemExit(f"decode reported stream errors: {np.flatnonzero(status)[:8]}")
@@ -283,8 +302,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"fptc-{args.workload}", "streams": int(len(sample_off) - 1),
                    "samples": n_samples, "window": q.N, "kept_coeffs": q.E, "quantizer": "amplitude 0.25/2.0/T16",
-                   "lmax": 12, "path": args.path, "precision": args.precision, "windows_per_chunk": args.wpc,
-                   "waves_per_block": args.waves, "compressed_bytes": int(comp_bytes),
+                   "lmax": 12, "path": args.path, "precision": args.precision,
+                   "windows_per_chunk": launch.windows_per_chunk, "waves_per_block": launch.waves_per_block,
+                   "blocks": launch.blocks, "hip_graph": bool(args.graph), "compressed_bytes": int(comp_bytes),
                    "bytes_per_sample_in": round(comp_bytes / n_samples, 4)},
         "roofline": roof,
         "path_roofline": {"algorithmic_bytes": int(path_alg), "achieved_GBs": round(path_alg / (ms_step * 1e-3) / 1e9, 1),
@@ -292,6 +312,7 @@ def main():
                           "roofline_decoded_GBs": round(path_roofline_decoded, 1),
                           "decoded_frac_of_roofline": round(value / path_roofline_decoded, 4)},
         "stage_ms": {k: round(float(v), 4) for k, v in zip(names, stage_ms)},
+        "autotune_ms": tuned,
         "gpu_ms_per_step": {"median": round(float(np.median(gpu_steps)), 4), "min": round(float(gpu_steps.min()), 4),
                             "max": round(float(gpu_steps.max()), 4)},
     }

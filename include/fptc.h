@@ -178,6 +178,21 @@ FPTC_API int32_t fptc_dequant_idct(const fptc_batch *batch, const fptc_codec *co
                           const void *ws, size_t ws_bytes, const uint8_t *symbols, const float *gamma,
                           int32_t precision, float *out, void *stream);
 
+/* Backward of fptc_dequant_idct for an output gradient grad_out = dL/dx
+ * (device [n_samples]; samples past a stream's length are not outputs).
+ *   grad_coeff (device [n_symbols] or NULL): dL/dchat for every coefficient,
+ *     chat = gamma * dequantized value, i.e. the first E bins of the
+ *     orthonormal DCT-II (Section 3.1) of each window of grad_out; FP32.
+ *   grad_gamma (device [n_streams][3] or NULL): dL/dgamma[s][z], the sum over
+ *     the stream's coefficients of zone z of dL/dchat * dequantized value,
+ *     accumulated in FP64 in a fixed order (deterministic).
+ * At least one output must be given.  Needs a plan in `ws` (its backward
+ * scratch is written); symbols as written by fptc_decode_batch. */
+FPTC_API int32_t fptc_dequant_idct_backward(const fptc_batch *batch, const fptc_codec *codec,
+                                            const fptc_launch *launch, void *ws, size_t ws_bytes,
+                                            const uint8_t *symbols, const float *grad_out, float *grad_coeff,
+                                            double *grad_gamma, void *stream);
+
 /* Decode, dequantize and inverse-transform in one pass: the two stages of
  * Section 4.2 fused, the decoded symbols of a chunk of windows kept in LDS
  * instead of a global array.  Same result as fptc_decode_batch followed by

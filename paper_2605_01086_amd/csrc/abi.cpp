@@ -154,6 +154,20 @@ int32_t fptc_dequant_idct(const fptc_batch *batch, const fptc_codec *codec, cons
   return status_of(launch_dqidct_mfma(*batch, *codec, s, pv, symbols, gamma, precision, out, stream));
 }
 
+int32_t fptc_dequant_idct_backward(const fptc_batch *batch, const fptc_codec *codec, const fptc_launch *launch,
+                                   void *ws, size_t ws_bytes, const uint8_t *symbols, const float *grad_out,
+                                   float *grad_coeff, double *grad_gamma, void *stream) {
+  Shape s;
+  int rc;
+  if ((rc = check_batch(batch)) || (rc = check_codec(codec)) || (rc = resolve_shape(launch, codec, &s))) return rc;
+  if (!ws || (!symbols && batch->n_symbols > 0) || (!grad_out && batch->n_samples > 0)) return FPTC_ERR_INVALID_ARG;
+  if (!grad_coeff && !grad_gamma) return FPTC_ERR_INVALID_ARG;
+  if (bwd_lds_bytes(*codec, s) > 160 * 1024) return FPTC_ERR_UNSUPPORTED;
+  Layout L = layout_for(batch, codec, s);
+  if (ws_bytes < L.total) return FPTC_ERR_WORKSPACE;
+  return status_of(launch_bwd(*batch, *codec, s, plan_view(ws, L), symbols, grad_out, grad_coeff, grad_gamma, stream));
+}
+
 int32_t fptc_decompress_batch(const fptc_batch *batch, const fptc_codec *codec, const fptc_launch *launch,
                               const void *ws, size_t ws_bytes, const float *gamma, int32_t precision, float *out,
                               int32_t *stream_status, void *stream) {

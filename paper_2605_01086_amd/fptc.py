@@ -63,6 +63,8 @@ _SIGS = {
                                            _vp, _vp, ctypes.c_int32, _vp, _vp]),
     "fptc_decompress_batch": (ctypes.c_int32, [_P(fptc_batch), _P(fptc_codec), _P(fptc_launch), _vp,
                                                ctypes.c_size_t, _vp, ctypes.c_int32, _vp, _vp, _vp]),
+    "fptc_dequant_idct_backward": (ctypes.c_int32, [_P(fptc_batch), _P(fptc_codec), _P(fptc_launch), _vp,
+                                                    ctypes.c_size_t, _vp, _vp, _vp, _vp, _vp]),
     "fptc_build_lut": (ctypes.c_int32, [_vp, ctypes.c_int32, _vp]),
     "fptc_canonical_codes": (ctypes.c_int32, [_vp, _vp]),
     "fptc_code_lengths": (ctypes.c_int32, [_vp, ctypes.c_int32, _vp]),
@@ -165,6 +167,12 @@ def fptc_dequant_idct(batch, codec, launch, ws, symbols, gamma, precision, out, 
                                                          ctypes.byref(launch), _ptr(ws),
                                                          ws.numel() * ws.element_size(), _ptr(symbols), _ptr(gamma),
                                                          int(precision), _ptr(out), _stream(stream)))
+
+
+def fptc_dequant_idct_backward(batch, codec, launch, ws, symbols, grad_out, grad_coeff, grad_gamma, stream=None):
+    _check("fptc_dequant_idct_backward", load().fptc_dequant_idct_backward(
+        ctypes.byref(batch), ctypes.byref(codec), ctypes.byref(launch), _ptr(ws), ws.numel() * ws.element_size(),
+        _ptr(symbols), _ptr(grad_out), _ptr(grad_coeff), _ptr(grad_gamma), _stream(stream)))
 
 
 def fptc_decompress_batch(batch, codec, launch, ws, gamma, precision, out, status, stream=None):

@@ -1,0 +1,151 @@
+"""GPU backward of dequant + IDCT against the FP64 oracle: coefficient and
+scale gradients, FP64 central finite differences, determinism, the autograd
+Function and the Adam refit of the zone scales."""
+import numpy as np
+import pytest
+
+from cases import build_case
+
+pytestmark = pytest.mark.gpu
+
+
+def _amp(N, E=None):
+    from oracle import oracle as O
+    return O.QuantParams("amp", N, N if E is None else E)
+
+
+def _decoder(c):
+    import torch
+    from gpu_helpers import qparams
+    from paper_2605_01086_amd import codec as C
+    words, symlen, word_off, sample_off = c.concat()
+    codec = C.DeviceCodec(np.stack([b.lengths for b in c.books]), qparams(c.p), 12)
+    batch = C.DeviceBatch(words, symlen, word_off, sample_off, c.p.N, c.p.E, c.book_id)
+    dec = C.Decoder(batch, codec)
+    dec.plan()
+    dec.decode()
+    torch.cuda.synchronize()
+    assert int((dec.status != 0).sum()) == 0
+    return dec
+
+
+def _grads(c, dec, gx_list):
+    import torch
+    from paper_2605_01086_amd import fptc as F
+    gx = torch.from_numpy(np.concatenate(gx_list).astype(np.float32)).cuda()
+    gc = torch.empty(dec.batch.n_symbols, dtype=torch.float32, device="cuda")
+    gg = torch.empty((dec.batch.n_streams, 3), dtype=torch.float64, device="cuda")
+    F.fptc_dequant_idct_backward(dec.batch.c, dec.codec.c, dec.lc, dec.ws, dec.symbols, gx, gc, gg)
+    torch.cuda.synchronize()
+    return gc.cpu().numpy(), gg.cpu().numpy()
+
+
+@pytest.mark.parametrize("N,E,doms", [(128, 128, ["power", "meteo"]), (64, 64, ["eeg", "seismic"]),
+                                      (32, 16, ["eeg"]), (256, 256, ["meteo"])])
+def test_backward_matches_oracle(N, E, doms):
+    from oracle import oracle as O
+    p = _amp(N, E)
+    lens = [N * 40, N * 17 + 5, 3, N * 64 + N - 1]
+    c = build_case(p, doms, lens, config_id=2000 + N, recon=False)
+    dec = _decoder(c)
+    rng = np.random.default_rng(N)
+    gx = [rng.standard_normal(len(x)) for x in c.signals]
+    gc, gg = _grads(c, dec, gx)
+    for i in range(len(lens)):
+        ogc, ogg = O.backward(c.symbols[i], len(c.signals[i]), p, gx[i].astype(np.float32).astype(np.float64))
+        s0, s1 = dec.batch.sym_off_h[i], dec.batch.sym_off_h[i + 1]
+        scale = max(1e-30, np.abs(ogc).max())
+        assert np.max(np.abs(gc[s0:s1] - ogc)) <= 1e-5 * scale, i
+        gscale = np.sum(np.abs(ogc) * np.abs([O.dequantize(sv, k % E, p) for k, sv in enumerate(c.symbols[i])])) + 1e-30
+        assert np.all(np.abs(gg[i] - ogg) <= 1e-6 * gscale), (i, gg[i], ogg)
+
+
+def test_scale_gradient_matches_fp64_central_differences():
+    from oracle import oracle as O
+    p = _amp(128)
+    c = build_case(p, ["power", "meteo"], [128 * 30 + 7, 128 * 22], config_id=2100, recon=False)
+    dec = _decoder(c)
+    M = sum(len(x) for x in c.signals)
+    gamma = np.array([[1.1, 0.9, 1.05], [0.95, 1.02, 0.99]])
+    gx = []
+    for i, x in enumerate(c.signals):
+        xh = O.reconstruct(c.symbols[i], len(x), p, gamma[i])
+        gx.append(2.0 * (xh - x.astype(np.float64)) / M)
+    _, gg = _grads(c, dec, gx)
+    h = 1e-6
+
+    def loss(g):
+        return sum(np.sum((O.reconstruct(c.symbols[i], len(x), p, g[i]) - x.astype(np.float64)) ** 2)
+                   for i, x in enumerate(c.signals)) / M
+
+    for i in range(2):
+        for z in range(3):
+            e = np.zeros_like(gamma)
+            e[i, z] = h
+            fd = (loss(gamma + e) - loss(gamma - e)) / (2 * h)
+            assert abs(fd - gg[i, z]) <= 1e-5 * max(1.0, abs(fd)), (i, z, fd, gg[i, z])
+    assert gg[0, 0] == 0.0 and gg[1, 0] == 0.0  # zero zone: value 0, gradient exactly 0
+
+
+def test_backward_is_deterministic():
+    p = _amp(64)
+    c = build_case(p, ["eeg", "seismic"], [64 * 500, 64 * 300 + 9], config_id=2200, recon=False)
+    dec = _decoder(c)
+    gx = [np.random.default_rng(1).standard_normal(len(x)) for x in c.signals]
+    a = _grads(c, dec, gx)
+    b = _grads(c, dec, gx)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp16x2"])
+def test_autograd_and_adam_refit(precision):
+    import torch
+    from oracle import oracle as O
+    from paper_2605_01086_amd import refit as R
+    p = _amp(128)
+    c = build_case(p, ["power", "meteo"], [128 * 64, 128 * 40, 128 * 9], config_id=2300, recon=False)
+    dec = _decoder(c)
+    x = torch.from_numpy(np.concatenate(c.signals)).cuda()
+    # autograd gradient of the MSE at gamma = 1 vs the oracle
+    g = torch.ones((3, 3), dtype=torch.float64, device="cuda", requires_grad=True)
+    loss = R.mse(R.DequantIDCT.apply(g, dec, precision), x)
+    loss.backward()
+    M = x.numel()
+    for i, xi in enumerate(c.signals):
+        xh = O.reconstruct(c.symbols[i], len(xi), p, None)
+        _, og = O.backward(c.symbols[i], len(xi), p, 2.0 * (xh - xi.astype(np.float64)) / M, want_coef=False)
+        np.testing.assert_allclose(g.grad[i].cpu().numpy(), og, rtol=1e-4, atol=1e-7 * max(1.0, np.abs(og).max()))
+    gamma, losses = R.refit(dec, x, steps=20, precision=precision)
+    assert losses[-1] <= losses[0]
+    # the same 20 Adam steps on the oracle's FP64 gradients; Adam normalises each
+    # gradient by its running RMS, so components whose gradient is near zero may
+    # take slightly different steps: compare losses and scales loosely
+    og, olosses = O.adam_refit(list(zip(c.symbols, c.signals)), p, steps=20)
+    np.testing.assert_allclose(losses, olosses, rtol=1e-3)
+    np.testing.assert_allclose(gamma.cpu().numpy(), og, atol=2e-3)
+
+
+def test_differentiation_workload_full_size_sampled():
+    """256 power/met streams of 2^18 samples at W = 128: full-size forward +
+    backward on the GPU, scale gradients of sampled streams against the oracle."""
+    import torch
+    from oracle import oracle as O
+    p = _amp(128)
+    lens = [1 << 18] * 256
+    c = build_case(p, ["power", "meteo"], lens, config_id=3, recon=False, threads=16)
+    dec = _decoder(c)
+    x = torch.from_numpy(np.concatenate(c.signals)).cuda()
+    xh = dec.dequant_idct(precision="fp16x2")
+    M = x.numel()
+    gx = (2.0 * (xh.double() - x.double()) / M).float()
+    from paper_2605_01086_amd import fptc as F
+    gg = torch.empty((256, 3), dtype=torch.float64, device="cuda")
+    F.fptc_dequant_idct_backward(dec.batch.c, dec.codec.c, dec.lc, dec.ws, dec.symbols, gx, None, gg)
+    torch.cuda.synchronize()
+    gg = gg.cpu().numpy()
+    gxh = gx.cpu().numpy()
+    for i in np.random.default_rng(0).choice(256, size=6, replace=False):
+        o0, o1 = dec.batch.sample_off_h[i], dec.batch.sample_off_h[i + 1]
+        _, og = O.backward(c.symbols[i], lens[i], p, gxh[o0:o1].astype(np.float64), want_coef=False)
+        scale = max(1e-30, np.abs(og).max())
+        assert np.all(np.abs(gg[i] - og) <= 1e-5 * scale), (i, gg[i], og)
