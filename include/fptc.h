@@ -198,7 +198,7 @@ FPTC_API int32_t fptc_dequant_idct_backward(const fptc_batch *batch, const fptc_
  * instead of a global array.  Same result as fptc_decode_batch followed by
  * fptc_dequant_idct with the same precision (bit-identical samples), without
  * the symbol array.  Precisions: the MFMA ones (FP16, FP16X2, BF16, BF16X3)
- * for N in {32, 64, 128}; FPTC_ERR_UNSUPPORTED otherwise.  Needs a plan in
+ * for N in {32, 64, 128, 256}; FPTC_ERR_UNSUPPORTED otherwise.  Needs a plan in
  * `ws`; decoding errors OR into stream_status (device [n_streams]). */
 FPTC_API int32_t fptc_decompress_batch(const fptc_batch *batch, const fptc_codec *codec, const fptc_launch *launch,
                                        const void *ws, size_t ws_bytes, const float *gamma, int32_t precision,

@@ -145,12 +145,16 @@ int32_t fptc_dequant_idct(const fptc_batch *batch, const fptc_codec *codec, cons
   if ((rc = check_batch(batch)) || (rc = check_codec(codec)) || (rc = resolve_shape(launch, codec, &s))) return rc;
   if (!ws || (!symbols && batch->n_symbols > 0) || (!out && batch->n_samples > 0)) return FPTC_ERR_INVALID_ARG;
   if (precision < FPTC_FP32_SIMT || precision > FPTC_BF16X3) return FPTC_ERR_INVALID_ARG;
-  if (precision != FPTC_FP32_SIMT && !mfma_supported(codec->N, codec->E, precision)) return FPTC_ERR_UNSUPPORTED;
+  const bool wide = codec->N == 256;
+  if (precision != FPTC_FP32_SIMT &&
+      !(wide ? mfma256_supported(codec->E, precision) : mfma_supported(codec->N, codec->E, precision)))
+    return FPTC_ERR_UNSUPPORTED;
   Layout L = layout_for(batch, codec, s);
   if (ws_bytes < L.total) return FPTC_ERR_WORKSPACE;
   Plan pv = plan_view(const_cast<void *>(ws), L);
   if (precision == FPTC_FP32_SIMT)
     return status_of(launch_dqidct(*batch, *codec, s, pv, symbols, gamma, precision, out, stream));
+  if (wide) return status_of(launch_dqidct_mfma256(*batch, *codec, s, pv, symbols, gamma, precision, out, stream));
   return status_of(launch_dqidct_mfma(*batch, *codec, s, pv, symbols, gamma, precision, out, stream));
 }
 
@@ -176,17 +180,22 @@ int32_t fptc_decompress_batch(const fptc_batch *batch, const fptc_codec *codec, 
   if ((rc = check_batch(batch)) || (rc = check_codec(codec)) || (rc = resolve_shape(launch, codec, &s))) return rc;
   if (!ws || (!out && batch->n_samples > 0)) return FPTC_ERR_INVALID_ARG;
   if (precision < FPTC_FP32_SIMT || precision > FPTC_BF16X3) return FPTC_ERR_INVALID_ARG;
-  if (s.auto_waves) {  // the most waves (up to 16) whose LDS fits
-    s.waves = 16;
-    while (s.waves > 1 && !fused_supported(codec->N, codec->E, precision, s.wpc, s.waves, codec->n_books, codec->n_rows, codec->lmax))
-      --s.waves;
+  const bool wide = codec->N == 256;
+  auto fits = [&](int waves) {
+    return wide ? fused256_supported(*codec, precision, s.wpc, waves)
+                : fused_supported(codec->N, codec->E, precision, s.wpc, waves, codec->n_books, codec->n_rows,
+                                  codec->lmax);
+  };
+  if (s.auto_waves) {  // the most waves (up to 16; 8 at N = 256) whose LDS fits
+    s.waves = wide ? 8 : 16;
+    while (s.waves > 1 && !fits(s.waves)) --s.waves;
   }
-  if (!fused_supported(codec->N, codec->E, precision, s.wpc, s.waves, codec->n_books, codec->n_rows, codec->lmax))
-    return FPTC_ERR_UNSUPPORTED;
+  if (!fits(s.waves)) return FPTC_ERR_UNSUPPORTED;
   Layout L = layout_for(batch, codec, s);
   if (ws_bytes < L.total) return FPTC_ERR_WORKSPACE;
-  return status_of(launch_fused(*batch, *codec, s, plan_view(const_cast<void *>(ws), L), gamma, precision, out,
-                                stream_status, stream));
+  Plan pv = plan_view(const_cast<void *>(ws), L);
+  if (wide) return status_of(launch_fused256(*batch, *codec, s, pv, gamma, precision, out, stream_status, stream));
+  return status_of(launch_fused(*batch, *codec, s, pv, gamma, precision, out, stream_status, stream));
 }
 
 }  // extern "C"

@@ -36,17 +36,18 @@ __host__ __device__ constexpr size_t mfma_lds_bytes(int bpieces, int N, int Kp, 
   return (size_t)bpieces * N * (Kp + 8) * 2 + (size_t)n_books * n_rows * 256 * 5 + (size_t)n_books * E + 16;
 }
 
-// S = Kp / 16 k-steps (Kp = E rounded up to 16), NT = N / 32 output row tiles.
-template <int PREC, int S, int NT>
-__global__ void __launch_bounds__(kThreads) k_dqidct_mfma(fptc_batch b, int E, int n_books, int n_rows,
+// NT = N / 32 output row tiles; S = Kp / 16 k-steps (Kp = E rounded up to 16).
+template <int PREC, int NT>
+__global__ void __launch_bounds__(kThreads) k_dqidct_mfma(fptc_batch b, int E, int S, int n_books, int n_rows,
                                                           const float *deq_val, const uint8_t *deq_zone,
                                                           const uint8_t *row_of_bin, const float *basis,
                                                           const int64_t *hdr, const int64_t *win_off,
                                                           const int32_t *tile_stream, const uint8_t *symbols,
                                                           const float *gamma, float *out) {
   using T = Traits<PREC>;
-  constexpr int N = NT * 32, Kp = S * 16, KH = Kp / 2;
-  constexpr int RS = Kp + 8;  // LDS row stride of a basis piece, in halves
+  constexpr int N = NT * 32;
+  const int Kp = S * 16, KH = Kp / 2;
+  const int RS = Kp + 8;  // LDS row stride of a basis piece, in halves
   constexpr int BP = T::kBPieces, AP = T::kAPieces;
   extern __shared__ __align__(16) unsigned char lds[];
   uint16_t *Bs = reinterpret_cast<uint16_t *>(lds);                         // [BP][N][RS]
@@ -141,12 +142,13 @@ __global__ void __launch_bounds__(kThreads) k_dqidct_mfma(fptc_batch b, int E, i
   }
 }
 
-template <int PREC, int S, int NT>
+template <int PREC, int NT>
 int launch_t(const fptc_batch &b, const fptc_codec &c, const Shape &sh, const Plan &p, const uint8_t *symbols,
              const float *gamma, float *out, void *stream) {
-  constexpr int N = NT * 32, Kp = S * 16;
+  constexpr int N = NT * 32;
+  const int S = (c.E + 15) / 16, Kp = S * 16;
   const size_t lds = mfma_lds_bytes(Traits<PREC>::kBPieces, N, Kp, c.n_books, c.n_rows, c.E);
-  auto kern = k_dqidct_mfma<PREC, S, NT>;
+  auto kern = k_dqidct_mfma<PREC, NT>;
   static bool attr_set = false;  // one attribute call per instantiation
   if (!attr_set) {
     if (hipFuncSetAttribute(reinterpret_cast<const void *>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -156,7 +158,7 @@ int launch_t(const fptc_batch &b, const fptc_codec &c, const Shape &sh, const Pl
   }
   const int per_cu = (int)((160 * 1024) / lds);
   int blocks = sh.blocks > 0 ? sh.blocks : device_cu_count() * (per_cu < 1 ? 1 : (per_cu > 8 ? 8 : per_cu));
-  hipLaunchKernelGGL(kern, dim3(blocks), dim3(kThreads), lds, (hipStream_t)stream, b, c.E, c.n_books, c.n_rows,
+  hipLaunchKernelGGL(kern, dim3(blocks), dim3(kThreads), lds, (hipStream_t)stream, b, c.E, S, c.n_books, c.n_rows,
                      c.deq_val, c.deq_zone, c.row_of_bin, c.basis, p.hdr, p.win_off, p.tile_stream, symbols, gamma,
                      out);
   return (int)hipGetLastError();
@@ -165,15 +167,12 @@ int launch_t(const fptc_batch &b, const fptc_codec &c, const Shape &sh, const Pl
 template <int PREC>
 int launch_prec(const fptc_batch &b, const fptc_codec &c, const Shape &sh, const Plan &p, const uint8_t *symbols,
                 const float *gamma, float *out, void *stream) {
-  const int S = (c.E + 15) / 16;
-#define FPTC_CASE(NV, SV) \
-  if (c.N == NV && S == SV) return launch_t<PREC, SV, NV / 32>(b, c, sh, p, symbols, gamma, out, stream);
-  FPTC_CASE(32, 1) FPTC_CASE(32, 2)
-  FPTC_CASE(64, 1) FPTC_CASE(64, 2) FPTC_CASE(64, 3) FPTC_CASE(64, 4)
-  FPTC_CASE(128, 1) FPTC_CASE(128, 2) FPTC_CASE(128, 3) FPTC_CASE(128, 4)
-  FPTC_CASE(128, 5) FPTC_CASE(128, 6) FPTC_CASE(128, 7) FPTC_CASE(128, 8)
-#undef FPTC_CASE
-  return (int)hipErrorInvalidValue;
+  switch (c.N) {
+    case 32: return launch_t<PREC, 1>(b, c, sh, p, symbols, gamma, out, stream);
+    case 64: return launch_t<PREC, 2>(b, c, sh, p, symbols, gamma, out, stream);
+    case 128: return launch_t<PREC, 4>(b, c, sh, p, symbols, gamma, out, stream);
+    default: return (int)hipErrorInvalidValue;
+  }
 }
 
 }  // namespace

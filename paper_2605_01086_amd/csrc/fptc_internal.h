@@ -84,6 +84,13 @@ bool fused_supported(int N, int E, int precision, int wpc, int waves, int n_book
 int launch_fused(const fptc_batch &b, const fptc_codec &c, const Shape &s, const Plan &p, const float *gamma,
                  int precision, float *out, int32_t *status, void *stream);
 
+bool mfma256_supported(int E, int precision);
+bool fused256_supported(const fptc_codec &c, int precision, int wpc, int waves);
+int launch_dqidct_mfma256(const fptc_batch &b, const fptc_codec &c, const Shape &s, const Plan &p,
+                          const uint8_t *symbols, const float *gamma, int precision, float *out, void *stream);
+int launch_fused256(const fptc_batch &b, const fptc_codec &c, const Shape &s, const Plan &p, const float *gamma,
+                    int precision, float *out, int32_t *status, void *stream);
+
 size_t bwd_lds_bytes(const fptc_codec &c, const Shape &s);
 int launch_bwd(const fptc_batch &b, const fptc_codec &c, const Shape &s, const Plan &p, const uint8_t *symbols,
                const float *grad_out, float *grad_coeff, double *grad_gamma, void *stream);

@@ -40,9 +40,10 @@ __host__ __device__ inline size_t fused_lds_bytes(int bpieces, int N, int E, int
          align16((size_t)n_books * n_rows * 256 * 5 + (size_t)n_books * E) + (size_t)waves * fused_wave_bytes(N, E, wpc);
 }
 
-template <int PREC, int S, int NT>
+template <int PREC, int NT>
 __global__ void __launch_bounds__(kMaxFusedThreads) k_fused(const uint64_t *__restrict__ words,
                                                             const uint8_t *__restrict__ symlen, int n_streams, int E,
+                                                            int S,
                                                             int lmax, int n_books, int n_rows, int wpc,
                                                             const uint16_t *lut_g, const float *deq_val,
                                                             const uint8_t *deq_zone, const uint8_t *row_of_bin,
@@ -50,7 +51,8 @@ __global__ void __launch_bounds__(kMaxFusedThreads) k_fused(const uint64_t *__re
                                                             const ChunkMeta *__restrict__ meta, const float *gamma,
                                                             float *out, int32_t *status) {
   using T = Traits<PREC>;
-  constexpr int N = NT * 32, Kp = S * 16, KH = Kp / 2, RS = Kp + 8;
+  constexpr int N = NT * 32;
+  const int Kp = S * 16, KH = Kp / 2, RS = Kp + 8;
   constexpr int AP = T::kAPieces;
   extern __shared__ __align__(16) unsigned char lds[];
   const int nthreads = blockDim.x, waves = nthreads >> 6;
@@ -150,12 +152,13 @@ int pieces_of(int precision) {
   return precision == FPTC_BF16X3 ? 3 : (precision == FPTC_FP16X2 ? 2 : 1);
 }
 
-template <int PREC, int S, int NT>
+template <int PREC, int NT>
 int launch_t(const fptc_batch &b, const fptc_codec &c, const Shape &sh, const Plan &p, const float *gamma, float *out,
              int32_t *status, void *stream) {
-  constexpr int N = NT * 32, Kp = S * 16;
+  constexpr int N = NT * 32;
+  const int S = (c.E + 15) / 16, Kp = S * 16;
   const size_t lds = fused_lds_bytes(Traits<PREC>::kBPieces, N, c.E, Kp, sh.wpc, sh.waves, c.n_books, c.n_rows, c.lmax);
-  auto kern = k_fused<PREC, S, NT>;
+  auto kern = k_fused<PREC, NT>;
   static bool attr_set = false;  // one attribute call per instantiation
   if (!attr_set) {
     if (hipFuncSetAttribute(reinterpret_cast<const void *>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -166,7 +169,7 @@ int launch_t(const fptc_batch &b, const fptc_codec &c, const Shape &sh, const Pl
   const int per_cu = (int)((160 * 1024) / lds);
   const int blocks = sh.blocks > 0 ? sh.blocks : device_cu_count() * (per_cu > 0 ? per_cu : 1);
   hipLaunchKernelGGL(kern, dim3(blocks), dim3(sh.waves * 64), lds, (hipStream_t)stream, b.words, b.symlen,
-                     b.n_streams, c.E, c.lmax, c.n_books, c.n_rows, sh.wpc, c.lut, c.deq_val, c.deq_zone,
+                     b.n_streams, c.E, S, c.lmax, c.n_books, c.n_rows, sh.wpc, c.lut, c.deq_val, c.deq_zone,
                      c.row_of_bin, c.basis, p.hdr, p.chunk_meta, gamma, out, status);
   return (int)hipGetLastError();
 }
@@ -174,15 +177,12 @@ int launch_t(const fptc_batch &b, const fptc_codec &c, const Shape &sh, const Pl
 template <int PREC>
 int launch_prec(const fptc_batch &b, const fptc_codec &c, const Shape &sh, const Plan &p, const float *gamma,
                 float *out, int32_t *status, void *stream) {
-  const int S = (c.E + 15) / 16;
-#define FPTC_CASE(NV, SV) \
-  if (c.N == NV && S == SV) return launch_t<PREC, SV, NV / 32>(b, c, sh, p, gamma, out, status, stream);
-  FPTC_CASE(32, 1) FPTC_CASE(32, 2)
-  FPTC_CASE(64, 1) FPTC_CASE(64, 2) FPTC_CASE(64, 3) FPTC_CASE(64, 4)
-  FPTC_CASE(128, 1) FPTC_CASE(128, 2) FPTC_CASE(128, 3) FPTC_CASE(128, 4)
-  FPTC_CASE(128, 5) FPTC_CASE(128, 6) FPTC_CASE(128, 7) FPTC_CASE(128, 8)
-#undef FPTC_CASE
-  return (int)hipErrorInvalidValue;
+  switch (c.N) {
+    case 32: return launch_t<PREC, 1>(b, c, sh, p, gamma, out, status, stream);
+    case 64: return launch_t<PREC, 2>(b, c, sh, p, gamma, out, status, stream);
+    case 128: return launch_t<PREC, 4>(b, c, sh, p, gamma, out, status, stream);
+    default: return (int)hipErrorInvalidValue;
+  }
 }
 
 }  // namespace

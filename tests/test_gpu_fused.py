@@ -16,7 +16,7 @@ def _amp(N, E=None, **kw):
 
 
 @pytest.mark.parametrize("prec", ["fp16x2", "bf16x3", "fp16", "bf16"])
-@pytest.mark.parametrize("N", [32, 64, 128])
+@pytest.mark.parametrize("N", [32, 64, 128, 256])
 def test_fused_equals_two_call_path(prec, N):
     rng = np.random.default_rng(N + 7)
     lens = list(np.floor(2.0 ** rng.uniform(5, 13, size=14)).astype(int)) + [1, N - 1, N, N + 1, 40 * N + 3]
@@ -39,7 +39,7 @@ def test_fused_launch_shapes(wpc, waves, blocks):
     check_parity(c, f, tol=1e-5, check_symbols=False)
 
 
-@pytest.mark.parametrize("N,E", [(32, 16), (64, 20), (128, 100)])
+@pytest.mark.parametrize("N,E", [(32, 16), (64, 20), (128, 100), (256, 180)])
 def test_fused_paper_quantizer_with_scales(N, E):
     p = paper_params(N, E, "eeg", 1600 + N)
     c = build_case(p, ["eeg", "seismic"], [N * 150 + 7, 3001, 5, N * 31], config_id=1600 + N, gamma=True)
@@ -59,6 +59,15 @@ def test_fused_flags_corrupt_streams_and_isolates_the_rest():
     assert res["status"][1] & F.FPTC_STREAM_BAD_COUNT
     assert res["status"][3] & F.FPTC_STREAM_BAD_SYMLEN
     check_parity(c, res, tol=1e-5, skip={1, 3}, check_symbols=False)
+
+
+@pytest.mark.parametrize("wpc,waves", [(32, 8), (64, 4), (7, 2)])
+def test_fused_window_256_launch_shapes(wpc, waves):
+    from paper_2605_01086_amd import codec as C
+    c = build_case(_amp(256, step_f=1.0, step_c=8.0, T=16.0), ["eeg"], [256 * 300 + 77, 256 * 33, 100],
+                   config_id=1800)
+    f = run_gpu(c, precision="fp16x2", fused=True, launch=C.Launch(wpc, waves, 0))
+    check_parity(c, f, tol=1e-5, check_symbols=False)
 
 
 def test_fused_full_size_plain_stream():

@@ -23,7 +23,7 @@ LOOSE = [("fp16", 2e-3), ("bf16", 2e-2)]
 
 
 @pytest.mark.parametrize("prec,tol", EXACT + LOOSE)
-@pytest.mark.parametrize("N", [32, 64, 128])
+@pytest.mark.parametrize("N", [32, 64, 128, 256])
 def test_mfma_variants_amplitude(prec, tol, N):
     rng = np.random.default_rng(N)
     lens = list(np.floor(2.0 ** rng.uniform(5, 13, size=12)).astype(int)) + [1, N - 1, N + 1, 33 * N]
@@ -33,7 +33,7 @@ def test_mfma_variants_amplitude(prec, tol, N):
 
 
 @pytest.mark.parametrize("prec,tol", EXACT)
-@pytest.mark.parametrize("N,E", [(32, 16), (64, 20), (64, 64), (128, 100)])
+@pytest.mark.parametrize("N,E", [(32, 16), (64, 20), (64, 64), (128, 100), (256, 200), (256, 256)])
 def test_mfma_variants_paper_quantizer_and_scales(prec, tol, N, E):
     # inexact dequantized values (mu-law) and per-zone scales exercise the coefficient split
     p = paper_params(N, E, "eeg", 1100 + N)
