@@ -53,6 +53,24 @@ def make_workload(name: str, threads: int):
         config_id, n = 0, 1
         lens = np.array([1 << 20], dtype=np.int64)
         dom = np.zeros(1, dtype=np.int64)
+    elif name == "large":
+        # 64 channels x 2^24 samples of EEG-like sources mixed by a random 64x64 matrix
+        config_id, n_ch, L = 4, 64, 1 << 24
+        rng = synth.stream_rng(config_id, 0)
+        src = np.empty((n_ch, L), dtype=np.float32)
+
+        def gen_src(i):
+            src[i] = synth.eeg_like(L, synth.stream_rng(config_id, 1 + i))
+
+        with ThreadPoolExecutor(threads) as ex:
+            list(ex.map(gen_src, range(n_ch)))
+        M = (rng.standard_normal((n_ch, n_ch)) / np.sqrt(n_ch)).astype(np.float32)
+        x = np.ascontiguousarray((M @ src).reshape(-1))
+        del src
+        sample_off = np.arange(n_ch + 1, dtype=np.int64) * L
+        tr_src = np.stack([synth.eeg_like(1 << 16, synth.training_rng(config_id, i)) for i in range(n_ch)])
+        train = [(M.astype(np.float64) @ tr_src).reshape(-1).astype(np.float32)]
+        return x, sample_off, np.zeros(n_ch, dtype=np.uint8), train
     else:
         raise SystemExit(f"unknown workload {name}")
     sample_off = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
@@ -207,7 +225,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="batch", choices=["batch", "plain"])
+    ap.add_argument("--workload", default="batch", choices=["batch", "plain", "large"])
     ap.add_argument("--precision", default="fp16x2", choices=["fp32", "fp16", "fp16x2", "bf16", "bf16x3"])
     ap.add_argument("--path", default="fused", choices=["fused", "split"],
                     help="fused: one decode+dequant+IDCT kernel; split: decode kernel then dequant+IDCT kernel")
@@ -228,7 +246,10 @@ def main():
     threads = host_threads()
     t_setup = time.perf_counter()
     from paper_2605_01086_amd import codec as C
-    q = C.quant_params("amp", 64, 64, step_fine=STEP_F, step_coarse=STEP_C, threshold=THRESH)
+    if args.workload == "large":  # window 256, coarse steps 1.0 / 8.0
+        q = C.quant_params("amp", 256, 256, step_fine=1.0, step_coarse=8.0, threshold=THRESH)
+    else:
+        q = C.quant_params("amp", 64, 64, step_fine=STEP_F, step_coarse=STEP_C, threshold=THRESH)
     x, sample_off, dom, train = make_workload(args.workload, threads)
     words, symlen, word_off, lens_tab = encode(x, sample_off, dom, train, q, threads)
     n_samples = int(sample_off[-1])
@@ -301,7 +322,7 @@ def main():
         "dtype": "f32" if args.precision == "fp32" else f"{args.precision} MFMA, f32 accumulate",
         "data": "synthetic",
         "config": {"workload": f"fptc-{args.workload}", "streams": int(len(sample_off) - 1),
-                   "samples": n_samples, "window": q.N, "kept_coeffs": q.E, "quantizer": "amplitude 0.25/2.0/T16",
+                   "samples": n_samples, "window": q.N, "kept_coeffs": q.E, "quantizer": f"amplitude {q.step_fine}/{q.step_coarse}/T{q.threshold:g}",
                    "lmax": 12, "path": args.path, "precision": args.precision,
                    "windows_per_chunk": launch.windows_per_chunk, "waves_per_block": launch.waves_per_block,
                    "blocks": launch.blocks, "hip_graph": bool(args.graph), "compressed_bytes": int(comp_bytes),

@@ -59,6 +59,48 @@ void or_dct_eq1(const double *x, int N, double *C) {
   }
 }
 
+/* The same transforms against a precomputed table cosv[k*N + n] =
+ * cos(pi/N (n + 1/2) k): the table holds exactly the values the per-term code
+ * evaluates and the sums run in the same order, so the results are identical
+ * (a pinned property); stream-level routines use it to avoid N*N cos calls per
+ * window. */
+static double *or_cos_table(int N) {
+  double *t = (double *)malloc(sizeof(double) * (size_t)N * (size_t)N);
+  for (int k = 0; k < N; ++k)
+    for (int n = 0; n < N; ++n) t[(size_t)k * N + n] = or_cosarg(n, k, N);
+  return t;
+}
+
+static void or_dct_ortho_t(const double *x, int N, const double *cosv, double *X) {
+  for (int k = 0; k < N; ++k) {
+    double s = 0.0;
+    for (int n = 0; n < N; ++n) s += x[n] * cosv[(size_t)k * N + n];
+    X[k] = or_alpha(k, N) * s;
+  }
+}
+
+static void or_idct_ortho_t(const double *X, int N, int E, const double *cosv, double *x) {
+  for (int n = 0; n < N; ++n) {
+    double s = 0.0;
+    for (int k = 0; k < E; ++k) s += or_alpha(k, N) * X[k] * cosv[(size_t)k * N + n];
+    x[n] = s;
+  }
+}
+
+/* Test hook: table-based transforms of one window (must equal or_dct_ortho /
+ * or_idct_ortho bit for bit). */
+void or_dct_ortho_tab(const double *x, int N, double *X) {
+  double *t = or_cos_table(N);
+  or_dct_ortho_t(x, N, t, X);
+  free(t);
+}
+
+void or_idct_ortho_tab(const double *X, int N, int E, double *x) {
+  double *t = or_cos_table(N);
+  or_idct_ortho_t(X, N, E, t, x);
+  free(t);
+}
+
 /* Inverse of the orthonormal DCT-II (a DCT-III) from the first E coefficients;
  * bins k >= E are the ones discarded by spectral truncation (Section 3.1) and
  * count as zero. */
@@ -428,14 +470,16 @@ void or_quantize_stream(const float *x, int64_t L, const or_qparams *p, uint8_t 
   int64_t nw = or_n_windows(L, N);
   double *win = (double *)malloc(sizeof(double) * (size_t)N);
   double *X = (double *)malloc(sizeof(double) * (size_t)N);
+  double *cosv = or_cos_table(N);
   for (int64_t w = 0; w < nw; ++w) {
     for (int n = 0; n < N; ++n) {
       int64_t i = w * N + n;
       win[n] = i < L ? (double)x[i] : 0.0;
     }
-    or_dct_ortho(win, N, X);
+    or_dct_ortho_t(win, N, cosv, X);
     for (int k = 0; k < E; ++k) symbols[w * E + k] = (uint8_t)or_quantize(X[k], k, p);
   }
+  free(cosv);
   free(win);
   free(X);
 }
@@ -446,14 +490,16 @@ void or_dct_stream(const float *x, int64_t L, int N, int E, double *coef) {
   int64_t nw = or_n_windows(L, N);
   double *win = (double *)malloc(sizeof(double) * (size_t)N);
   double *X = (double *)malloc(sizeof(double) * (size_t)N);
+  double *cosv = or_cos_table(N);
   for (int64_t w = 0; w < nw; ++w) {
     for (int n = 0; n < N; ++n) {
       int64_t i = w * N + n;
       win[n] = i < L ? (double)x[i] : 0.0;
     }
-    or_dct_ortho(win, N, X);
+    or_dct_ortho_t(win, N, cosv, X);
     for (int k = 0; k < E; ++k) coef[w * E + k] = X[k];
   }
+  free(cosv);
   free(win);
   free(X);
 }
@@ -474,18 +520,20 @@ void or_reconstruct(const uint8_t *symbols, int64_t L, const or_qparams *p, cons
   int64_t nw = or_n_windows(L, N);
   double *X = (double *)malloc(sizeof(double) * (size_t)E);
   double *x = (double *)malloc(sizeof(double) * (size_t)N);
+  double *cosv = or_cos_table(N);
   for (int64_t w = 0; w < nw; ++w) {
     for (int k = 0; k < E; ++k) {
       int s = symbols[w * E + k];
       double g = gamma ? gamma[or_zone(s, k, p)] : 1.0;
       X[k] = g * or_dequantize(s, k, p);
     }
-    or_idct_ortho(X, N, E, x);
+    or_idct_ortho_t(X, N, E, cosv, x);
     for (int n = 0; n < N; ++n) {
       int64_t i = w * N + n;
       if (i < L) out[i] = x[n];
     }
   }
+  free(cosv);
   free(X);
   free(x);
 }
@@ -501,19 +549,21 @@ void or_backward(const uint8_t *symbols, int64_t L, const or_qparams *p, const d
   int64_t nw = or_n_windows(L, N);
   double *g = (double *)malloc(sizeof(double) * (size_t)N);
   double *G = (double *)malloc(sizeof(double) * (size_t)N);
+  double *cosv = or_cos_table(N);
   grad_gamma[0] = grad_gamma[1] = grad_gamma[2] = 0.0;
   for (int64_t w = 0; w < nw; ++w) {
     for (int n = 0; n < N; ++n) {
       int64_t i = w * N + n;
       g[n] = i < L ? gx[i] : 0.0;
     }
-    or_dct_ortho(g, N, G);
+    or_dct_ortho_t(g, N, cosv, G);
     for (int k = 0; k < E; ++k) {
       int s = symbols[w * E + k];
       if (grad_coef) grad_coef[w * E + k] = G[k];
       grad_gamma[or_zone(s, k, p)] += G[k] * or_dequantize(s, k, p);
     }
   }
+  free(cosv);
   free(g);
   free(G);
 }

@@ -61,6 +61,8 @@ def lib():
         L.or_dct_ortho.argtypes = [dp, ctypes.c_int, dp]
         L.or_dct_eq1.argtypes = [dp, ctypes.c_int, dp]
         L.or_idct_ortho.argtypes = [dp, ctypes.c_int, ctypes.c_int, dp]
+        L.or_dct_ortho_tab.argtypes = [dp, ctypes.c_int, dp]
+        L.or_idct_ortho_tab.argtypes = [dp, ctypes.c_int, ctypes.c_int, dp]
         L.or_quant_amp.argtypes = [ctypes.c_double] * 4
         L.or_quant_amp.restype = ctypes.c_int
         L.or_dequant_amp.argtypes = [ctypes.c_int] + [ctypes.c_double] * 3
@@ -154,6 +156,21 @@ def dct_eq1(x: np.ndarray) -> np.ndarray:
     x = np.ascontiguousarray(x, dtype=np.float64)
     out = np.empty_like(x)
     lib().or_dct_eq1(_ptr(x, ctypes.c_double), x.shape[0], _ptr(out, ctypes.c_double))
+    return out
+
+
+def dct_ortho_tab(x: np.ndarray) -> np.ndarray:
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    out = np.empty_like(x)
+    lib().or_dct_ortho_tab(_ptr(x, ctypes.c_double), x.shape[0], _ptr(out, ctypes.c_double))
+    return out
+
+
+def idct_ortho_tab(X: np.ndarray, N: int, E: int | None = None) -> np.ndarray:
+    X = np.ascontiguousarray(X, dtype=np.float64)
+    E = X.shape[0] if E is None else E
+    out = np.empty(N, dtype=np.float64)
+    lib().or_idct_ortho_tab(_ptr(X, ctypes.c_double), N, E, _ptr(out, ctypes.c_double))
     return out
 
 

@@ -58,3 +58,14 @@ def test_stream_windows_and_zero_padded_tail(O):
     pad = np.zeros(6 * N)
     pad[:L] = x
     np.testing.assert_allclose(coef, sfft.dct(pad.reshape(6, N), type=2, norm="ortho", axis=1), atol=1e-12)
+
+
+@pytest.mark.parametrize("N,E", [(4, 4), (64, 64), (64, 20), (256, 256)])
+def test_table_transforms_equal_per_term_transforms_bitwise(O, N, E):
+    # stream-level routines use a precomputed cosine table; it must change nothing
+    rng = np.random.default_rng(N + E)
+    for _ in range(5):
+        x = rng.standard_normal(N) * 100
+        assert np.array_equal(O.dct_ortho_tab(x), O.dct_ortho(x))
+        X = rng.standard_normal(E) * 100
+        assert np.array_equal(O.idct_ortho_tab(X, N, E), O.idct_ortho(X, N, E))
