@@ -116,7 +116,8 @@ typedef struct {
 typedef struct {
   int32_t windows_per_chunk;  /* windows per decode work item (chunk); default 32 */
   int32_t waves_per_block;    /* 0: default (4; fptc_decompress_batch: the most, up to 16,
-                                 whose LDS fits); at most 16 */
+                                 8 at N >= 128, whose LDS fits); at most 16 (fused: 8 at
+                                 N >= 128, else FPTC_ERR_UNSUPPORTED) */
   int32_t blocks;             /* persistent grid size; default: enough to fill the GPU */
   int32_t reserved0;
 } fptc_launch;

@@ -147,7 +147,7 @@ int32_t fptc_dequant_idct(const fptc_batch *batch, const fptc_codec *codec, cons
   if (precision < FPTC_FP32_SIMT || precision > FPTC_BF16X3) return FPTC_ERR_INVALID_ARG;
   const bool wide = codec->N == 256;
   if (precision != FPTC_FP32_SIMT &&
-      !(wide ? mfma256_supported(codec->E, precision) : mfma_supported(codec->N, codec->E, precision)))
+      !(wide ? mfma256_supported(codec->E, precision) : mfma_supported(codec->N, codec->E, precision, codec->n_books, codec->n_rows)))
     return FPTC_ERR_UNSUPPORTED;
   Layout L = layout_for(batch, codec, s);
   if (ws_bytes < L.total) return FPTC_ERR_WORKSPACE;
@@ -186,7 +186,7 @@ int32_t fptc_decompress_batch(const fptc_batch *batch, const fptc_codec *codec, 
                 : fused_supported(codec->N, codec->E, precision, s.wpc, waves, codec->n_books, codec->n_rows,
                                   codec->lmax);
   };
-  if (s.auto_waves) {  // the most waves (up to 16; 8 at N = 256) whose LDS fits
+  if (s.auto_waves) {  // the most waves (up to 16; 8 at N = 128 and 256) whose LDS fits
     s.waves = wide ? 8 : 16;
     while (s.waves > 1 && !fits(s.waves)) --s.waves;
   }

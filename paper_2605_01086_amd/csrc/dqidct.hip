@@ -47,7 +47,7 @@ __global__ void __launch_bounds__(kThreads) k_dqidct_f32(fptc_batch b, int N, in
                                                          const float *deq_val, const uint8_t *deq_zone,
                                                          const uint8_t *row_of_bin, const float *basis,
                                                          const int64_t *hdr, const int64_t *win_off,
-                                                         const uint8_t *symbols, const float *gamma, float *out) {
+                                                         const uint8_t *symbols, const float *__restrict__ gamma, float *out) {
   extern __shared__ __align__(16) unsigned char lds[];
   const int TW = kTileOut / N;  // windows per tile
   const int kKB = bins_per_block(N);

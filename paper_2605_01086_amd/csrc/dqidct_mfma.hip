@@ -1,7 +1,8 @@
 // Dequantization fused with the inverse DCT on the matrix cores (Section 4.2,
 // lossy stage, as a dense contraction).
 //
-// For a tile of 32 consecutive windows (global numbering) one wavefront forms
+// For a tile of up to 32 consecutive windows of one stream (a chunk of the
+// plan, or a 32-window part of it) one wavefront forms
 //     D[n][w] = sum_k B[k][n] * c[w][k]
 // i.e. the transposed product basis^T x coefficients^T, with
 // v_mfma_f32_32x32x16_{f16,bf16}: FP32 accumulation, 16-bit operands.  The
@@ -18,9 +19,9 @@
 //           per-zone scale != 1) is split too, and the pass with its lo piece
 //           is skipped when every lane's lo piece is zero.
 //   BF16X3: basis = hi + mid + lo in BF16, coefficients likewise.
-// The basis pieces live in LDS (rows padded by 16 bytes to spread banks); the
-// dequantization tables live in LDS; coefficients are dequantized in registers
-// straight from the decoded symbols.
+// The basis pieces live in LDS (rows padded by 16 bytes to spread banks), as do
+// the dequantization tables and each wave's tile of symbols; coefficients are
+// dequantized in registers from the symbols (tile_contract).
 #include <hip/hip_runtime.h>
 
 #include "fptc_internal.h"
@@ -30,30 +31,95 @@ namespace fptc {
 namespace {
 
 constexpr int kThreads = 256;
+constexpr int kWaves = kThreads / 64;
 
-// LDS bytes of one instantiation: basis pieces and tables.
-__host__ __device__ constexpr size_t mfma_lds_bytes(int bpieces, int N, int Kp, int n_books, int n_rows, int E) {
-  return (size_t)bpieces * N * (Kp + 8) * 2 + (size_t)n_books * n_rows * 256 * 5 + (size_t)n_books * E + 16;
+__host__ __device__ constexpr size_t a16(size_t x) { return (x + 15) & ~(size_t)15; }
+
+__host__ __device__ constexpr size_t table_bytes(int bpieces, int n_books, int n_rows, int E) {
+  return a16((size_t)n_books * n_rows * 256 * 5 + (size_t)n_books * E) +
+         (bpieces <= 2 ? a16((size_t)n_books * n_rows * 256 * 4) : 0);
 }
 
-// NT = N / 32 output row tiles; S = Kp / 16 k-steps (Kp = E rounded up to 16).
+// LDS bytes of one instantiation: basis pieces, tables, one 32-window symbol
+// tile per wave.
+__host__ __device__ constexpr size_t mfma_lds_bytes(int bpieces, int N, int Kp, int n_books, int n_rows, int E) {
+  return (size_t)bpieces * N * (Kp + 8) * 2 + table_bytes(bpieces, n_books, n_rows, E) +
+         (size_t)kWaves * a16((size_t)kTileWindows * E + 16);
+}
+
+// The symbols of a 32-window tile, 16 bytes per lane per round: R rounds of
+// 64 lanes cover 32 windows of E <= 32 R symbols.
+template <int R>
+struct TileSyms {
+  uint4 v[R];
+};
+
+template <int R>
+__device__ inline void load_tile_syms(const uint8_t *__restrict__ symbols, int64_t n_symbols, int64_t base,
+                                      int nbytes, bool vec16, int lane, TileSyms<R> &t) {
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int off = 16 * (lane + 64 * r);
+    t.v[r] = make_uint4(0u, 0u, 0u, 0u);
+    if (off < nbytes) {
+      const int64_t g = base + off;
+      if (vec16 && g + 16 <= n_symbols) {
+        t.v[r] = *reinterpret_cast<const uint4 *>(symbols + g);
+      } else {
+        uint32_t w[4] = {0u, 0u, 0u, 0u};
+        for (int j = 0; j < 16; ++j)
+          if (g + j < n_symbols) w[j >> 2] |= (uint32_t)symbols[g + j] << (8 * (j & 3));
+        t.v[r] = make_uint4(w[0], w[1], w[2], w[3]);
+      }
+    }
+  }
+}
+
+template <int R>
+__device__ inline void put_tile_syms(unsigned char *sb, int nbytes, int lane, const TileSyms<R> &t) {
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int off = 16 * (lane + 64 * r);
+    if (off < nbytes) *reinterpret_cast<uint4 *>(sb + off) = t.v[r];
+  }
+}
+
+// Pin the wait for prefetched symbols here (see settle_chunk_words).
+template <int R>
+__device__ inline void settle_tile_syms(const TileSyms<R> &t) {
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+    asm volatile("" ::"v"(t.v[r].x), "v"(t.v[r].y), "v"(t.v[r].z), "v"(t.v[r].w) : "memory");
+}
+
+// Work item = one chunk of the plan (up to wpc consecutive windows of one
+// stream), in 32-window tiles; NT = N / 32 output row tiles, S = Kp / 16
+// k-steps (Kp = E rounded up to 16).  A tile's symbols are one contiguous run:
+// they are staged into the wave's LDS buffer with 16-byte loads, the first
+// tile of the next chunk being loaded while this chunk computes.
 template <int PREC, int NT>
-__global__ void __launch_bounds__(kThreads) k_dqidct_mfma(fptc_batch b, int E, int S, int n_books, int n_rows,
-                                                          const float *deq_val, const uint8_t *deq_zone,
-                                                          const uint8_t *row_of_bin, const float *basis,
-                                                          const int64_t *hdr, const int64_t *win_off,
-                                                          const int32_t *tile_stream, const uint8_t *symbols,
-                                                          const float *gamma, float *out) {
+__global__ void __launch_bounds__(kThreads, NT >= 4 ? 2 : (NT == 2 ? 3 : 4)) k_dqidct_mfma(fptc_batch b, int E, int S, int n_books, int n_rows,
+                                                          const float *__restrict__ deq_val,
+                                                          const uint8_t *__restrict__ deq_zone,
+                                                          const uint8_t *__restrict__ row_of_bin,
+                                                          const float *__restrict__ basis,
+                                                          const int64_t *__restrict__ hdr,
+                                                          const ChunkMeta *__restrict__ meta,
+                                                          const uint8_t *__restrict__ symbols,
+                                                          const float *__restrict__ gamma, float *out) {
   using T = Traits<PREC>;
   constexpr int N = NT * 32;
-  const int Kp = S * 16, KH = Kp / 2;
+  const int Kp = S * 16;
   const int RS = Kp + 8;  // LDS row stride of a basis piece, in halves
   constexpr int BP = T::kBPieces, AP = T::kAPieces;
   extern __shared__ __align__(16) unsigned char lds[];
-  uint16_t *Bs = reinterpret_cast<uint16_t *>(lds);                         // [BP][N][RS]
-  float *Tv = reinterpret_cast<float *>(lds + (size_t)BP * N * RS * 2);      // [books][rows][256]
-  uint8_t *Tz = reinterpret_cast<uint8_t *>(Tv + n_books * n_rows * 256);    // [books][rows][256]
-  uint8_t *Rb = Tz + n_books * n_rows * 256;                                 // [books][E]
+  uint16_t *Bs = reinterpret_cast<uint16_t *>(lds);                       // [BP][N][RS]
+  float *Tv = reinterpret_cast<float *>(lds + (size_t)BP * N * RS * 2);    // [books][rows][256]
+  uint8_t *Tz = reinterpret_cast<uint8_t *>(Tv + n_books * n_rows * 256);  // [books][rows][256]
+  uint8_t *Rb = Tz + n_books * n_rows * 256;                               // [books][E]
+  uint32_t *Pq = reinterpret_cast<uint32_t *>(reinterpret_cast<unsigned char *>(Tv) +
+                                              a16((size_t)n_books * n_rows * 256 * 5 + (size_t)n_books * E));
+  unsigned char *bufs = reinterpret_cast<unsigned char *>(Tv) + table_bytes(BP, n_books, n_rows, E);
 
   // Stage the split basis (transposed to [n][k], zero beyond E) and the tables.
   const float bscale = T::kF16 ? kBasisScaleF16 : 1.0f;
@@ -67,78 +133,72 @@ __global__ void __launch_bounds__(kThreads) k_dqidct_mfma(fptc_batch b, int E, i
     const int r = row_of_bin[i];
     Rb[i] = (uint8_t)(r < n_rows ? r : n_rows - 1);
   }
+  if constexpr (AP <= 2) stage_pieces<PREC>(Pq, deq_val, n_books * n_rows * 256, threadIdx.x, kThreads);
   __syncthreads();
 
   const int lane = threadIdx.x & 63, col = lane & 31, h = lane >> 5;
-  const int wid = threadIdx.x >> 6;
-  const int64_t n_win = hdr[1];
-  const int64_t n_tiles = (n_win + kTileWindows - 1) / kTileWindows;
-  const int64_t stride = (int64_t)gridDim.x * (kThreads / 64);
+  const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  unsigned char *sb = bufs + (size_t)wid * a16((size_t)kTileWindows * E + 16);
+  const int64_t n_chunks = hdr[0];
+  const int64_t cstride = (int64_t)gridDim.x * kWaves;
   const float oscale = 1.0f / bscale;
-  const bool e_vec = (E % 16) == 0 && (reinterpret_cast<uintptr_t>(symbols) & 7) == 0;
+  const bool vec16 = (E % 16) == 0 && (reinterpret_cast<uintptr_t>(symbols) & 15) == 0;
 
-  for (int64_t tile = (int64_t)blockIdx.x * (kThreads / 64) + wid; tile < n_tiles; tile += stride) {
-    // ---- window of this lane's column
-    const int64_t g = tile * kTileWindows + col;
-    int valid = 0, book = 0;
-    int64_t obase = 0;
-    float gz0 = 1.0f, gz1 = 1.0f, gz2 = 1.0f;
-    if (g < n_win) {
-      int s = tile_stream[tile];
-      s = s < 0 ? 0 : (s >= b.n_streams ? b.n_streams - 1 : s);
-      while (s + 1 < b.n_streams && win_off[s + 1] <= g) ++s;
-      const int64_t j = g - win_off[s];
-      const int64_t L = b.sample_off[s + 1] - b.sample_off[s];
-      const int64_t o = b.sample_off[s] + j * N;
-      int64_t v = L - j * N;
-      v = v < N ? v : N;
-      if (o < 0 || o + v > b.n_samples || j < 0) v = 0;
-      valid = v > 0 ? (int)v : 0;
-      obase = o;
-      const int bk = b.book_id ? (int)b.book_id[s] : 0;
-      book = bk < n_books ? bk : 0;
-      if (gamma) {
-        gz0 = gamma[3 * (int64_t)s];
-        gz1 = gamma[3 * (int64_t)s + 1];
-        gz2 = gamma[3 * (int64_t)s + 2];
-      }
+  int64_t c = (int64_t)blockIdx.x * kWaves + wid;
+  ChunkMeta cm{}, nm{};
+  cm.n_windows = nm.n_windows = 0;
+  TileSyms<NT> cur{};
+  if (c < n_chunks) {
+    cm = meta[c];
+    load_tile_syms(symbols, b.n_symbols, cm.sym_base, min(kTileWindows, cm.n_windows) * E, vec16, lane, cur);
+  }
+  if (c + cstride < n_chunks) nm = meta[c + cstride];
+  for (; c < n_chunks; c += cstride) {
+    TileSyms<NT> nx{};
+    if (c + cstride < n_chunks)
+      load_tile_syms(symbols, b.n_symbols, nm.sym_base, min(kTileWindows, nm.n_windows) * E, vec16, lane, nx);
+    ChunkMeta mm{};
+    mm.n_windows = 0;
+    if (c + 2 * cstride < n_chunks) mm = meta[c + 2 * cstride];
+    const int s = cm.stream < 0 ? 0 : (cm.stream >= b.n_streams ? b.n_streams - 1 : cm.stream);
+    const int book = cm.book < n_books && cm.book >= 0 ? cm.book : 0;
+    const int w_cnt = cm.n_windows;
+    float g0 = 1.0f, g1 = 1.0f, g2 = 1.0f;
+    if (gamma) {
+      g0 = gamma[3 * (int64_t)s];
+      g1 = gamma[3 * (int64_t)s + 1];
+      g2 = gamma[3 * (int64_t)s + 2];
     }
-    // ---- contraction, one k-step at a time from the highest bins down
-    f16v acc[NT];
-#pragma unroll
-    for (int t = 0; t < NT; ++t)
-#pragma unroll
-      for (int r = 0; r < 16; ++r) acc[t][r] = 0.0f;
-    const int64_t sbase = g * (int64_t)E + h * KH;
-#pragma unroll 1
-    for (int s = S - 1; s >= 0; --s) {
-      const int k0 = h * KH + 8 * s;
-      uint8_t sy[8];
-      if (valid > 0 && e_vec && sbase + 8 * s + 8 <= b.n_symbols) {
-        const uint2 u = *reinterpret_cast<const uint2 *>(symbols + sbase + 8 * s);
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          sy[j] = (uint8_t)(u.x >> (8 * j));
-          sy[4 + j] = (uint8_t)(u.y >> (8 * j));
-        }
+    for (int tt = 0; tt * kTileWindows < w_cnt; ++tt) {
+      const int wt = min(kTileWindows, w_cnt - tt * kTileWindows);
+      if (tt == 0) {
+        put_tile_syms(sb, wt * E, lane, cur);
       } else {
-#pragma unroll
-        for (int j = 0; j < 8; ++j) {
-          const int64_t si = sbase + 8 * s + j;
-          sy[j] = (valid > 0 && k0 + j < E && si < b.n_symbols) ? symbols[si] : (uint8_t)128;
-        }
+        TileSyms<NT> t;
+        load_tile_syms(symbols, b.n_symbols, cm.sym_base + (int64_t)tt * kTileWindows * E, wt * E, vec16, lane, t);
+        put_tile_syms(sb, wt * E, lane, t);
       }
-      u8v a[AP];
-      const bool r = dequant8<PREC>(sy, k0, E, valid > 0, Rb + book * E, Tv + book * n_rows * 256,
-                                    Tz + book * n_rows * 256, gamma != nullptr, gz0, gz1, gz2, a);
-      const bool any_rest = AP > 1 && __any(r);
-      mfma_step<PREC, NT>(acc, a, Bs + col * RS + k0, 32 * RS, N * RS, any_rest);
-    }
-    // lane holds rows n = t*32 + 8*q + 4*h + (0..3) of its window
-    if (valid > 0) {
+      wave_sync_lds();
+      const int wr = tt * kTileWindows + col;
+      const int valid = col < wt ? min(N, cm.out_len - wr * N) : 0;
+      const int base = (col < wt ? col : wt - 1) * E;
+      f16v acc[NT];
+      tile_contract<PREC, NT>(acc, sb, base, h, col, S, E, valid > 0, Bs, RS, Rb + book * E,
+                              Tv + book * n_rows * 256, Tz + book * n_rows * 256, Pq + book * n_rows * 256, n_rows,
+                              gamma, g0, g1, g2);
+      if (tt == 0) settle_tile_syms(nx);  // before this chunk's stores
+      // lane holds rows n = t*32 + 8*q + 4*h + (0..3) of its window
+      if (valid > 0) {
+        float *dst = out + cm.out_base + (int64_t)wr * N;
 #pragma unroll
-      for (int t = 0; t < NT; ++t) store_block(out + obase, acc[t], t * 32, h, valid, oscale);
+        for (int t = 0; t < NT; ++t) store_block(dst, acc[t], t * 32, h, valid, oscale);
+      }
+      wave_sync_lds();
     }
+    settle_tile_syms(nx);
+    cur = nx;
+    cm = nm;
+    nm = mm;
   }
 }
 
@@ -159,8 +219,7 @@ int launch_t(const fptc_batch &b, const fptc_codec &c, const Shape &sh, const Pl
   const int per_cu = (int)((160 * 1024) / lds);
   int blocks = sh.blocks > 0 ? sh.blocks : device_cu_count() * (per_cu < 1 ? 1 : (per_cu > 8 ? 8 : per_cu));
   hipLaunchKernelGGL(kern, dim3(blocks), dim3(kThreads), lds, (hipStream_t)stream, b, c.E, S, c.n_books, c.n_rows,
-                     c.deq_val, c.deq_zone, c.row_of_bin, c.basis, p.hdr, p.win_off, p.tile_stream, symbols, gamma,
-                     out);
+                     c.deq_val, c.deq_zone, c.row_of_bin, c.basis, p.hdr, p.chunk_meta, symbols, gamma, out);
   return (int)hipGetLastError();
 }
 
@@ -177,14 +236,14 @@ int launch_prec(const fptc_batch &b, const fptc_codec &c, const Shape &sh, const
 
 }  // namespace
 
-bool mfma_supported(int N, int E, int precision) {
+bool mfma_supported(int N, int E, int precision, int n_books, int n_rows) {
   if (precision < FPTC_FP16 || precision > FPTC_BF16X3) return false;
   if (N != 32 && N != 64 && N != 128) return false;
   if (E < 1 || E > N) return false;
-  // LDS: basis pieces + tables must fit in 160 KB (staging is optional)
+  // LDS: basis pieces, tables and the waves' symbol tiles must fit in 160 KB
   const int Kp = (E + 15) / 16 * 16;
   const int pieces = precision == FPTC_BF16X3 ? 3 : (precision == FPTC_FP16X2 ? 2 : 1);
-  return mfma_lds_bytes(pieces, N, Kp, kMaxBooks, kMaxRows, E) <= 160 * 1024;
+  return mfma_lds_bytes(pieces, N, Kp, n_books, n_rows, E) <= 160 * 1024;
 }
 
 int launch_dqidct_mfma(const fptc_batch &b, const fptc_codec &c, const Shape &s, const Plan &p,

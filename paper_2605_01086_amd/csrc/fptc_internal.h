@@ -76,7 +76,7 @@ int launch_decode(const fptc_batch &b, const fptc_codec &c, const Shape &s, cons
 int launch_dqidct(const fptc_batch &b, const fptc_codec &c, const Shape &s, const Plan &p,
                   const uint8_t *symbols, const float *gamma, int precision, float *out, void *stream);
 
-bool mfma_supported(int N, int E, int precision);
+bool mfma_supported(int N, int E, int precision, int n_books, int n_rows);
 int launch_dqidct_mfma(const fptc_batch &b, const fptc_codec &c, const Shape &s, const Plan &p,
                        const uint8_t *symbols, const float *gamma, int precision, float *out, void *stream);
 

@@ -7,9 +7,10 @@
 //  1. decode: 64 words at a time, one word per lane (the paper's one thread per
 //     word), run offsets from a DPP wavefront prefix sum of symlen, each lane
 //     decoding exactly symlen[w] symbols with lmax-bit peeks into the
-//     codebook's lookup table in LDS.  Symbols of the chunk land in a per-wave
-//     LDS buffer in window-major order; the next 64 words are loaded while the
-//     current ones decode.
+//     codebook's lookup table in LDS (up to three symbols per peek when the
+//     multi-symbol table fits).  Symbols of the chunk land in a per-wave LDS
+//     buffer in window-major order.  The first 128 words of the next chunk are
+//     loaded while this chunk is processed, later rounds one round ahead.
 //  2. per 32 windows: dequantize from LDS into split 16-bit operands, contract
 //     with the split IDCT basis on v_mfma_f32_32x32x16 (exactly the arithmetic
 //     of the stand-alone MFMA kernel, so results are bit-identical) and store
@@ -25,47 +26,64 @@ namespace {
 
 __host__ __device__ constexpr size_t align16(size_t x) { return (x + 15) & ~(size_t)15; }
 
-constexpr int kMaxFusedWaves = 16;
-constexpr int kMaxFusedThreads = kMaxFusedWaves * 64;
+// Waves per block: up to 16; up to 8 at N = 128, whose basis leaves LDS for
+// no more than that and whose four output tiles need the registers.
+__host__ __device__ constexpr int max_fused_waves(int N) { return N >= 128 ? 8 : 16; }
 
-// Per-wave LDS region: the chunk's decoded symbols.
-__host__ __device__ inline size_t fused_wave_bytes(int N, int E, int wpc) {
-  (void)N;
-  return align16((size_t)wpc * E + 16);
+// Per-wave LDS region: a prefix for symbols of the previous chunk, then the
+// chunk's decoded symbols.
+__host__ __device__ inline size_t fused_wave_bytes(int E, int wpc) {
+  return (size_t)kSymPrefix + align16((size_t)wpc * E + 16);
 }
 
-__host__ __device__ inline size_t fused_lds_bytes(int bpieces, int N, int E, int Kp, int wpc, int waves, int n_books,
-                                                  int n_rows, int lmax) {
-  return align16((size_t)(n_books << lmax) * 2) + (size_t)bpieces * N * (Kp + 8) * 2 +
-         align16((size_t)n_books * n_rows * 256 * 5 + (size_t)n_books * E) + (size_t)waves * fused_wave_bytes(N, E, wpc);
+// Dequantization tables: values, zones, row of each bin and, for at most two
+// pieces, the pre-split values.
+__host__ __device__ inline size_t fused_table_bytes(int bpieces, int n_books, int n_rows, int E) {
+  return align16((size_t)n_books * n_rows * 256 * 5 + (size_t)n_books * E) +
+         (bpieces <= 2 ? align16((size_t)n_books * n_rows * 256 * 4) : 0);
 }
 
-template <int PREC, int NT>
-__global__ void __launch_bounds__(kMaxFusedThreads) k_fused(const uint64_t *__restrict__ words,
+// LDS: lookup tables | split basis | dequantization tables | wave buffers.
+// The multi-symbol build borrows lut1_temp_bytes right after the tables.
+__host__ __device__ inline size_t fused_lds_bytes(bool ms, int bpieces, int N, int E, int Kp, int wpc, int waves,
+                                                  int n_books, int n_rows, int lmax) {
+  const size_t t = lut_lds_bytes(ms, n_books, lmax);
+  const size_t need = t + (size_t)bpieces * N * (Kp + 8) * 2 + fused_table_bytes(bpieces, n_books, n_rows, E) +
+                      (size_t)waves * fused_wave_bytes(E, wpc);
+  const size_t tmp = ms ? t + lut1_temp_bytes(n_books, lmax) : 0;
+  return need > tmp ? need : tmp;
+}
+
+template <int PREC, int NT, bool MS>
+__global__ void __launch_bounds__(64 * max_fused_waves(NT * 32)) k_fused(const uint64_t *__restrict__ words,
                                                             const uint8_t *__restrict__ symlen, int n_streams, int E,
-                                                            int S,
-                                                            int lmax, int n_books, int n_rows, int wpc,
-                                                            const uint16_t *lut_g, const float *deq_val,
-                                                            const uint8_t *deq_zone, const uint8_t *row_of_bin,
-                                                            const float *basis, const int64_t *hdr,
-                                                            const ChunkMeta *__restrict__ meta, const float *gamma,
-                                                            float *out, int32_t *status) {
+                                                            int S, int lmax, int n_books, int n_rows, int wpc,
+                                                            const uint16_t *__restrict__ lut_g,
+                                                            const float *__restrict__ deq_val,
+                                                            const uint8_t *__restrict__ deq_zone,
+                                                            const uint8_t *__restrict__ row_of_bin,
+                                                            const float *__restrict__ basis,
+                                                            const int64_t *__restrict__ hdr,
+                                                            const ChunkMeta *__restrict__ meta,
+                                                            const float *__restrict__ gamma, float *out,
+                                                            int32_t *status) {
   using T = Traits<PREC>;
   constexpr int N = NT * 32;
   const int Kp = S * 16, KH = Kp / 2, RS = Kp + 8;
   constexpr int AP = T::kAPieces;
   extern __shared__ __align__(16) unsigned char lds[];
   const int nthreads = blockDim.x, waves = nthreads >> 6;
-  uint16_t *lut = reinterpret_cast<uint16_t *>(lds);
-  uint16_t *Bs = reinterpret_cast<uint16_t *>(lds + align16((size_t)(n_books << lmax) * 2));
+  const size_t lut_bytes = lut_lds_bytes(MS, n_books, lmax);
+  uint16_t *Bs = reinterpret_cast<uint16_t *>(lds + lut_bytes);
   float *Tv = reinterpret_cast<float *>(Bs + (size_t)T::kBPieces * N * RS);
   uint8_t *Tz = reinterpret_cast<uint8_t *>(Tv + n_books * n_rows * 256);
   uint8_t *Rb = Tz + n_books * n_rows * 256;
-  unsigned char *wave_base = reinterpret_cast<unsigned char *>(Tv) + align16((size_t)n_books * n_rows * 256 * 5 +
-                                                                             (size_t)n_books * E);
+  uint32_t *Pq = reinterpret_cast<uint32_t *>(reinterpret_cast<unsigned char *>(Tv) +
+                                              align16((size_t)n_books * n_rows * 256 * 5 + (size_t)n_books * E));
+  unsigned char *wave_base = reinterpret_cast<unsigned char *>(Tv) + fused_table_bytes(AP, n_books, n_rows, E);
 
   // ---- block setup: lookup tables, basis pieces, dequantization tables
-  stage_lut(lut, lut_g, n_books << lmax, threadIdx.x, nthreads);
+  stage_decode_tables(MS, lds, lds + lut_bytes, lut_g, lmax, n_books, threadIdx.x, nthreads);
   stage_basis<PREC>(Bs, basis, N, E, Kp, RS, threadIdx.x, nthreads);
   for (int i = threadIdx.x; i < n_books * n_rows * 256; i += nthreads) {
     Tv[i] = deq_val[i];
@@ -76,75 +94,85 @@ __global__ void __launch_bounds__(kMaxFusedThreads) k_fused(const uint64_t *__re
     const int r = row_of_bin[i];
     Rb[i] = (uint8_t)(r < n_rows ? r : n_rows - 1);
   }
+  if constexpr (AP <= 2) stage_pieces<PREC>(Pq, deq_val, n_books * n_rows * 256, threadIdx.x, nthreads);
   __syncthreads();
 
   const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63, col = lane & 31, h = lane >> 5;
-  unsigned char *sb = wave_base + (size_t)wid * fused_wave_bytes(N, E, wpc);
+  unsigned char *sb = wave_base + (size_t)wid * fused_wave_bytes(E, wpc) + kSymPrefix;
+  const uint8_t *cl = lds + ((size_t)n_books << lmax) * 4;
   const int hs = 32 - lmax;  // peek = top lmax bits of the word = hi32 >> hs
   const float oscale = 1.0f / (T::kF16 ? kBasisScaleF16 : 1.0f);
-  const bool e_vec = (E % 16) == 0;
   const int64_t n_chunks = hdr[0];
+  const int64_t cstride = (int64_t)gridDim.x * waves;
 
-  for (int64_t c = (int64_t)blockIdx.x * waves + wid; c < n_chunks; c += (int64_t)gridDim.x * waves) {
-    const ChunkMeta cm = meta[c];
-    if (cm.first_word < 0) continue;  // the stream's symbol count is wrong; already flagged
+  // Software pipeline over this wave's chunks c, c + cstride, ...: the words
+  // of chunk i+1 are requested before chunk i decodes (their meta one chunk
+  // earlier still) and are waited for right after that decode, before chunk
+  // i's stores.  Vector memory counters retire in order, so this one wait
+  // also covers chunk i-1's stores, which had the whole decode to drain.
+  int64_t c = (int64_t)blockIdx.x * waves + wid;
+  ChunkMeta cm{}, nm{};
+  cm.first_word = nm.first_word = -1;
+  ChunkWords cw{};
+  if (c < n_chunks) {
+    cm = meta[c];
+    load_chunk_words(words, symlen, cm.first_word, cm.word_end, lane, cw);
+  }
+  if (c + cstride < n_chunks) nm = meta[c + cstride];
+  for (; c < n_chunks; c += cstride) {
+    ChunkWords nx{};
+    if (c + cstride < n_chunks) load_chunk_words(words, symlen, nm.first_word, nm.word_end, lane, nx);
+    ChunkMeta mm{};
+    mm.first_word = -1;
+    if (c + 2 * cstride < n_chunks) mm = meta[c + 2 * cstride];
+    const bool ok = cm.first_word >= 0;  // else the stream's symbol count is wrong; already flagged
     const int s = cm.stream < 0 ? 0 : (cm.stream >= n_streams ? n_streams - 1 : cm.stream);
-    const int book = cm.book < n_books ? cm.book : 0;
+    const int book = cm.book < n_books && cm.book >= 0 ? cm.book : 0;
     const int w_cnt = cm.n_windows;
-    float g0 = 1.0f, g1 = 1.0f, g2 = 1.0f;
-    if (gamma) {
-      g0 = gamma[3 * (int64_t)s];
-      g1 = gamma[3 * (int64_t)s + 1];
-      g2 = gamma[3 * (int64_t)s + 2];
-    }
 
     // ---- 1. decode the chunk's symbols into sb[0 .. w_cnt * E)
-    const int err = decode_range(words, symlen, cm.first_word, cm.first_sym, w_cnt * E, cm.word_end,
-                                 lut + (book << lmax), hs, sb, lane);
-    if (err && status) atomicOr(&status[s], err);
-    wave_sync_lds();
-
-    // ---- 2. per 32 windows: dequantize, contract, store
-    for (int tt = 0; tt * kTileWindows < w_cnt; ++tt) {
-      const int wr = tt * kTileWindows + col;  // chunk-relative window of this lane's column
-      const int valid = wr < w_cnt ? min(N, cm.out_len - wr * N) : 0;
-      // windows past the chunk read the last window's symbols (discarded)
-      const int base = (wr < w_cnt ? wr : w_cnt - 1) * E;
-      f16v acc[NT];
-#pragma unroll
-      for (int t = 0; t < NT; ++t)
-#pragma unroll
-        for (int r = 0; r < 16; ++r) acc[t][r] = 0.0f;
-#pragma unroll 1
-      for (int ss = S - 1; ss >= 0; --ss) {
-        const int k0 = h * KH + 8 * ss;
-        uint8_t sy[8];
-        if (e_vec) {  // E % 16 == 0: the 8-bin group is inside [0, E) and 8-byte aligned
-          const uint2 u = *reinterpret_cast<const uint2 *>(sb + base + k0);
-#pragma unroll
-          for (int j = 0; j < 4; ++j) {
-            sy[j] = (uint8_t)(u.x >> (8 * j));
-            sy[4 + j] = (uint8_t)(u.y >> (8 * j));
-          }
-        } else {
-#pragma unroll
-          for (int j = 0; j < 8; ++j) sy[j] = sb[base + (k0 + j < E ? k0 + j : 0)];
-        }
-        u8v a[AP];
-        const bool r = dequant8<PREC>(sy, k0, E, valid > 0, Rb + book * E, Tv + book * n_rows * 256,
-                                      Tz + book * n_rows * 256, gamma != nullptr, g0, g1, g2, a);
-        const bool any_rest = AP > 1 && __any(r);
-        mfma_step<PREC, NT>(acc, a, Bs + col * RS + k0, 32 * RS, N * RS, any_rest);
-      }
-      // this lane's window starts at out_base + wr * N; all windows of a chunk
-      // are consecutive in one stream
-      if (valid > 0) {
-        float *dst = out + cm.out_base + (int64_t)wr * N;
-#pragma unroll
-        for (int t = 0; t < NT; ++t) store_block(dst, acc[t], t * 32, h, valid, oscale);
-      }
+    int err = 0;
+    if (ok) {
+      const void *lb = MS ? (const void *)(reinterpret_cast<const uint32_t *>(lds) + (book << lmax))
+                          : (const void *)(reinterpret_cast<const uint16_t *>(lds) + (book << lmax));
+      err = decode_chunk<MS>(words, symlen, cm.first_word, cm.first_sym, w_cnt * E, cm.word_end, cw, lb,
+                             cl + book * 256, hs, sb, lane);
     }
+    settle_chunk_words(nx);
+    cw = nx;
+    if (ok) {
+      if (err && status) atomicOr(&status[s], err);
+      float g0 = 1.0f, g1 = 1.0f, g2 = 1.0f;
+      if (gamma) {
+        g0 = gamma[3 * (int64_t)s];
+        g1 = gamma[3 * (int64_t)s + 1];
+        g2 = gamma[3 * (int64_t)s + 2];
+      }
+      wave_sync_lds();
+
+      // ---- 2. per 32 windows: dequantize, contract, store
+      for (int tt = 0; tt * kTileWindows < w_cnt; ++tt) {
+        const int wr = tt * kTileWindows + col;  // chunk-relative window of this lane's column
+        const int valid = wr < w_cnt ? min(N, cm.out_len - wr * N) : 0;
+        // windows past the chunk read the last window's symbols (discarded)
+        const int base = (wr < w_cnt ? wr : w_cnt - 1) * E;
+        f16v acc[NT];
+        tile_contract<PREC, NT>(acc, sb, base, h, col, S, E, valid > 0, Bs, RS, Rb + book * E,
+                                Tv + book * n_rows * 256, Tz + book * n_rows * 256, Pq + book * n_rows * 256, n_rows,
+                                gamma, g0, g1, g2);
+        // this lane's window starts at out_base + wr * N; all windows of a
+        // chunk are consecutive in one stream
+        if (valid > 0) {
+          float *dst = out + cm.out_base + (int64_t)wr * N;
+#pragma unroll
+          for (int t = 0; t < NT; ++t) store_block(dst, acc[t], t * 32, h, valid, oscale);
+        }
+      }
+      wave_sync_lds();
+    }
+    cm = nm;
+    nm = mm;
   }
 }
 
@@ -152,13 +180,14 @@ int pieces_of(int precision) {
   return precision == FPTC_BF16X3 ? 3 : (precision == FPTC_FP16X2 ? 2 : 1);
 }
 
-template <int PREC, int NT>
+template <int PREC, int NT, bool MS>
 int launch_t(const fptc_batch &b, const fptc_codec &c, const Shape &sh, const Plan &p, const float *gamma, float *out,
              int32_t *status, void *stream) {
   constexpr int N = NT * 32;
   const int S = (c.E + 15) / 16, Kp = S * 16;
-  const size_t lds = fused_lds_bytes(Traits<PREC>::kBPieces, N, c.E, Kp, sh.wpc, sh.waves, c.n_books, c.n_rows, c.lmax);
-  auto kern = k_fused<PREC, NT>;
+  const size_t lds =
+      fused_lds_bytes(MS, Traits<PREC>::kBPieces, N, c.E, Kp, sh.wpc, sh.waves, c.n_books, c.n_rows, c.lmax);
+  auto kern = k_fused<PREC, NT, MS>;
   static bool attr_set = false;  // one attribute call per instantiation
   if (!attr_set) {
     if (hipFuncSetAttribute(reinterpret_cast<const void *>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -174,13 +203,24 @@ int launch_t(const fptc_batch &b, const fptc_codec &c, const Shape &sh, const Pl
   return (int)hipGetLastError();
 }
 
+// Multi-symbol decode tables when they fit beside everything else.
+template <int PREC, int NT>
+int launch_ms(const fptc_batch &b, const fptc_codec &c, const Shape &sh, const Plan &p, const float *gamma,
+              float *out, int32_t *status, void *stream) {
+  const int Kp = (c.E + 15) / 16 * 16;
+  if (fused_lds_bytes(true, Traits<PREC>::kBPieces, NT * 32, c.E, Kp, sh.wpc, sh.waves, c.n_books, c.n_rows,
+                      c.lmax) <= 160 * 1024)
+    return launch_t<PREC, NT, true>(b, c, sh, p, gamma, out, status, stream);
+  return launch_t<PREC, NT, false>(b, c, sh, p, gamma, out, status, stream);
+}
+
 template <int PREC>
 int launch_prec(const fptc_batch &b, const fptc_codec &c, const Shape &sh, const Plan &p, const float *gamma,
                 float *out, int32_t *status, void *stream) {
   switch (c.N) {
-    case 32: return launch_t<PREC, 1>(b, c, sh, p, gamma, out, status, stream);
-    case 64: return launch_t<PREC, 2>(b, c, sh, p, gamma, out, status, stream);
-    case 128: return launch_t<PREC, 4>(b, c, sh, p, gamma, out, status, stream);
+    case 32: return launch_ms<PREC, 1>(b, c, sh, p, gamma, out, status, stream);
+    case 64: return launch_ms<PREC, 2>(b, c, sh, p, gamma, out, status, stream);
+    case 128: return launch_ms<PREC, 4>(b, c, sh, p, gamma, out, status, stream);
     default: return (int)hipErrorInvalidValue;
   }
 }
@@ -189,11 +229,11 @@ int launch_prec(const fptc_batch &b, const fptc_codec &c, const Shape &sh, const
 
 bool fused_supported(int N, int E, int precision, int wpc, int waves, int n_books, int n_rows, int lmax) {
   if (precision < FPTC_FP16 || precision > FPTC_BF16X3) return false;
-  if (waves < 1 || waves > kMaxFusedWaves) return false;
+  if (waves < 1 || waves > max_fused_waves(N)) return false;
   if (N != 32 && N != 64 && N != 128) return false;
   if (E < 1 || E > N) return false;
   const int Kp = (E + 15) / 16 * 16;
-  return fused_lds_bytes(pieces_of(precision), N, E, Kp, wpc, waves, n_books, n_rows, lmax) <= 160 * 1024;
+  return fused_lds_bytes(false, pieces_of(precision), N, E, Kp, wpc, waves, n_books, n_rows, lmax) <= 160 * 1024;
 }
 
 int launch_fused(const fptc_batch &b, const fptc_codec &c, const Shape &s, const Plan &p, const float *gamma,

@@ -47,7 +47,10 @@ __device__ inline void stage_basis_block(uint16_t *Bb, const float *basis, int E
 }
 
 // Contract k-steps [s0, s1) of one 32-window tile against the staged block;
-// symbols come from `sym(k0)` (8 symbols of bins k0 .. k0 + 7).
+// symbols come from `sym(k0)`: the 8 symbols of bins k0 .. k0 + 7, byte j of
+// the pair being bin k0 + j.  (The pre-split table of the resident kernels
+// is not used here: with eight 32-row output tiles the accumulators already
+// take half of the 256 registers a wave has at eight waves per block.)
 template <int PREC, typename SymFn>
 __device__ inline void contract_block256(f16v (&acc)[NT256], const uint16_t *Bb, int s0, int s1, int KH, int h,
                                          int col, int E, bool valid, const uint8_t *rb, const float *tv,
@@ -57,8 +60,13 @@ __device__ inline void contract_block256(f16v (&acc)[NT256], const uint16_t *Bb,
 #pragma unroll 1
   for (int s = s1 - 1; s >= s0; --s) {
     const int k0 = h * KH + 8 * s;
+    const uint2 u = sym(k0);
     uint8_t sy[8];
-    sym(k0, sy);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      sy[j] = (uint8_t)(u.x >> (8 * j));
+      sy[4 + j] = (uint8_t)(u.y >> (8 * j));
+    }
     u8v a[AP];
     const bool r = dequant8<PREC>(sy, k0, E, valid, rb, tv, tz, scaled, g0, g1, g2, a);
     const bool any_rest = AP > 1 && __any(r);
@@ -74,7 +82,7 @@ __global__ void __launch_bounds__(kMaxWaves256 * 64) k_dqidct_mfma256(fptc_batch
                                                                        const uint8_t *row_of_bin, const float *basis,
                                                                        const int64_t *hdr, const int64_t *win_off,
                                                                        const int32_t *tile_stream,
-                                                                       const uint8_t *symbols, const float *gamma,
+                                                                       const uint8_t *symbols, const float *__restrict__ gamma,
                                                                        float *out) {
   using T = Traits<PREC>;
   extern __shared__ __align__(16) unsigned char lds[];
@@ -130,12 +138,15 @@ __global__ void __launch_bounds__(kMaxWaves256 * 64) k_dqidct_mfma256(fptc_batch
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[t][r] = 0.0f;
     const int64_t sbase = g * (int64_t)E;
-    auto sym = [&](int k0, uint8_t(&sy)[8]) {
+    auto sym = [&](int k0) {
+      uint32_t w[2] = {0u, 0u};
 #pragma unroll
       for (int j = 0; j < 8; ++j) {
         const int64_t si = sbase + k0 + j;
-        sy[j] = (valid > 0 && k0 + j < E && si < b.n_symbols) ? symbols[si] : (uint8_t)128;
+        const uint32_t v = (valid > 0 && k0 + j < E && si < b.n_symbols) ? symbols[si] : 128u;
+        w[j >> 2] |= v << (8 * (j & 3));
       }
+      return make_uint2(w[0], w[1]);
     };
     for (int blk = nblk - 1; blk >= 0; --blk) {
       __syncthreads();
@@ -153,26 +164,48 @@ __global__ void __launch_bounds__(kMaxWaves256 * 64) k_dqidct_mfma256(fptc_batch
 }
 
 // ---------------------------------------------------------------- fused path
-template <int PREC>
+// Dequantization tables: values, zones, row of each bin.
+__host__ __device__ inline size_t table256_bytes(int bp, int n_books, int n_rows, int E) {
+  (void)bp;
+  return a16((size_t)n_books * n_rows * 256 * 5 + (size_t)n_books * E);
+}
+
+__host__ __device__ inline size_t wave256_bytes(int wpc, int E) { return (size_t)kSymPrefix + a16((size_t)wpc * E + 16); }
+
+// LDS: lookup tables | staged basis block | dequantization tables | wave
+// buffers; the multi-symbol build borrows lut1_temp_bytes after the tables.
+__host__ __device__ inline size_t fused256_lds_ms(bool ms, int bp, int n_books, int lmax, int E, int wpc, int waves,
+                                                  int n_rows) {
+  const size_t t = lut_lds_bytes(ms, n_books, lmax);
+  const size_t need = t + block_basis_bytes(bp) + table256_bytes(bp, n_books, n_rows, E) +
+                      (size_t)waves * wave256_bytes(wpc, E);
+  const size_t tmp = ms ? t + lut1_temp_bytes(n_books, lmax) : 0;
+  return need > tmp ? need : tmp;
+}
+
+template <int PREC, bool MS>
 __global__ void __launch_bounds__(kMaxWaves256 * 64) k_fused256(const uint64_t *__restrict__ words,
                                                                  const uint8_t *__restrict__ symlen, int n_streams,
                                                                  int E, int S, int lmax, int n_books, int n_rows,
-                                                                 int wpc, const uint16_t *lut_g, const float *deq_val,
-                                                                 const uint8_t *deq_zone, const uint8_t *row_of_bin,
-                                                                 const float *basis, const int64_t *hdr,
+                                                                 int wpc, const uint16_t *__restrict__ lut_g,
+                                                                 const float *__restrict__ deq_val,
+                                                                 const uint8_t *__restrict__ deq_zone,
+                                                                 const uint8_t *__restrict__ row_of_bin,
+                                                                 const float *__restrict__ basis,
+                                                                 const int64_t *__restrict__ hdr,
                                                                  const ChunkMeta *__restrict__ meta,
-                                                                 const float *gamma, float *out, int32_t *status) {
+                                                                 const float *__restrict__ gamma, float *out,
+                                                                 int32_t *status) {
   using T = Traits<PREC>;
   extern __shared__ __align__(16) unsigned char lds[];
   const int nthreads = blockDim.x, waves = nthreads >> 6;
-  uint16_t *lut = reinterpret_cast<uint16_t *>(lds);
-  uint16_t *Bb = reinterpret_cast<uint16_t *>(lds + a16((size_t)(n_books << lmax) * 2));
+  const size_t lut_bytes = lut_lds_bytes(MS, n_books, lmax);
+  uint16_t *Bb = reinterpret_cast<uint16_t *>(lds + lut_bytes);
   float *Tv = reinterpret_cast<float *>(reinterpret_cast<unsigned char *>(Bb) + block_basis_bytes(T::kBPieces));
   uint8_t *Tz = reinterpret_cast<uint8_t *>(Tv + n_books * n_rows * 256);
   uint8_t *Rb = Tz + n_books * n_rows * 256;
-  unsigned char *wave_base =
-      reinterpret_cast<unsigned char *>(Tv) + a16((size_t)n_books * n_rows * 256 * 5 + (size_t)n_books * E);
-  stage_lut(lut, lut_g, n_books << lmax, threadIdx.x, nthreads);
+  unsigned char *wave_base = reinterpret_cast<unsigned char *>(Tv) + table256_bytes(T::kBPieces, n_books, n_rows, E);
+  stage_decode_tables(MS, lds, lds + lut_bytes, lut_g, lmax, n_books, threadIdx.x, nthreads);
   for (int i = threadIdx.x; i < n_books * n_rows * 256; i += nthreads) {
     Tv[i] = deq_val[i];
     const int z = deq_zone[i];
@@ -183,35 +216,60 @@ __global__ void __launch_bounds__(kMaxWaves256 * 64) k_fused256(const uint64_t *
     Rb[i] = (uint8_t)(r < n_rows ? r : n_rows - 1);
   }
   __syncthreads();
+  const bool e_vec = (E % 16) == 0;
   const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63, col = lane & 31, h = lane >> 5;
-  unsigned char *sb = wave_base + (size_t)wid * a16((size_t)wpc * E + 16);
+  unsigned char *sb = wave_base + (size_t)wid * wave256_bytes(wpc, E) + kSymPrefix;
+  const uint8_t *cl = lds + ((size_t)n_books << lmax) * 4;
   const int hs = 32 - lmax;
   const int KH = S * 8, nblk = (S + kSB - 1) / kSB;
   const int ntile_max = (wpc + kTileWindows - 1) / kTileWindows;
   const float oscale = 1.0f / (T::kF16 ? kBasisScaleF16 : 1.0f);
   const int64_t n_chunks = hdr[0];
+  const int64_t cstride = (int64_t)gridDim.x * waves;
 
-  for (int64_t c0 = (int64_t)blockIdx.x * waves; c0 < n_chunks; c0 += (int64_t)gridDim.x * waves) {
+  // Software pipeline over this wave's chunks (see the resident fused
+  // kernel): next chunk's words requested before this chunk decodes, waited
+  // for right after the decode, before this chunk's stores.
+  ChunkMeta cm{}, nm{};
+  cm.first_word = nm.first_word = -1;
+  cm.n_windows = 0;
+  ChunkWords cw{};
+  {
+    const int64_t c = (int64_t)blockIdx.x * waves + wid;
+    if (c < n_chunks) {
+      cm = meta[c];
+      load_chunk_words(words, symlen, cm.first_word, cm.word_end, lane, cw);
+    }
+    if (c + cstride < n_chunks) nm = meta[c + cstride];
+  }
+  for (int64_t c0 = (int64_t)blockIdx.x * waves; c0 < n_chunks; c0 += cstride) {
     const int64_t c = c0 + wid;
-    ChunkMeta cm;
-    cm.first_word = -1;
-    cm.n_windows = 0;
-    if (c < n_chunks) cm = meta[c];
-    const bool active = cm.first_word >= 0;
+    ChunkWords nx{};
+    if (c + cstride < n_chunks) load_chunk_words(words, symlen, nm.first_word, nm.word_end, lane, nx);
+    ChunkMeta mm{};
+    mm.first_word = -1;
+    mm.n_windows = 0;
+    if (c + 2 * cstride < n_chunks) mm = meta[c + 2 * cstride];
+    const bool active = c < n_chunks && cm.first_word >= 0;
     const int s = cm.stream < 0 ? 0 : (cm.stream >= n_streams ? n_streams - 1 : cm.stream);
     const int book = cm.book < n_books && cm.book >= 0 ? cm.book : 0;
     const int w_cnt = active ? cm.n_windows : 0;
+    int err = 0;
+    if (active) {
+      const void *lb = MS ? (const void *)(reinterpret_cast<const uint32_t *>(lds) + (book << lmax))
+                          : (const void *)(reinterpret_cast<const uint16_t *>(lds) + (book << lmax));
+      err = decode_chunk<MS>(words, symlen, cm.first_word, cm.first_sym, w_cnt * E, cm.word_end, cw, lb,
+                             cl + book * 256, hs, sb, lane);
+    }
+    settle_chunk_words(nx);
+    cw = nx;
+    if (err && status) atomicOr(&status[s], err);
     float g0 = 1.0f, g1 = 1.0f, g2 = 1.0f;
     if (active && gamma) {
       g0 = gamma[3 * (int64_t)s];
       g1 = gamma[3 * (int64_t)s + 1];
       g2 = gamma[3 * (int64_t)s + 2];
-    }
-    if (active) {
-      const int err = decode_range(words, symlen, cm.first_word, cm.first_sym, w_cnt * E, cm.word_end,
-                                   lut + (book << lmax), hs, sb, lane);
-      if (err && status) atomicOr(&status[s], err);
     }
     wave_sync_lds();
     for (int tt = 0; tt < ntile_max; ++tt) {
@@ -224,9 +282,12 @@ __global__ void __launch_bounds__(kMaxWaves256 * 64) k_fused256(const uint64_t *
 #pragma unroll
         for (int r = 0; r < 16; ++r) acc[t][r] = 0.0f;
       const bool tile_active = tt * kTileWindows < w_cnt;
-      auto sym = [&](int k0, uint8_t(&sy)[8]) {
+      auto sym = [&](int k0) {
+        if (e_vec) return *reinterpret_cast<const uint2 *>(sb + base + k0);
+        uint32_t w[2] = {0u, 0u};
 #pragma unroll
-        for (int j = 0; j < 8; ++j) sy[j] = sb[base + (k0 + j < E ? k0 + j : 0)];
+        for (int j = 0; j < 8; ++j) w[j >> 2] |= (uint32_t)sb[base + (k0 + j < E ? k0 + j : 0)] << (8 * (j & 3));
+        return make_uint2(w[0], w[1]);
       };
       for (int blk = nblk - 1; blk >= 0; --blk) {
         __syncthreads();
@@ -244,6 +305,8 @@ __global__ void __launch_bounds__(kMaxWaves256 * 64) k_fused256(const uint64_t *
       }
     }
     wave_sync_lds();
+    cm = nm;
+    nm = mm;
   }
 }
 
@@ -254,8 +317,7 @@ size_t split256_lds(int bp, const fptc_codec &c) {
 }
 
 size_t fused256_lds(int bp, const fptc_codec &c, int wpc, int waves, int n_rows) {
-  return a16((size_t)(c.n_books << c.lmax) * 2) + block_basis_bytes(bp) +
-         a16((size_t)c.n_books * n_rows * 256 * 5 + (size_t)c.n_books * c.E) + (size_t)waves * a16((size_t)wpc * c.E + 16);
+  return fused256_lds_ms(false, bp, c.n_books, c.lmax, c.E, wpc, waves, n_rows);
 }
 
 template <typename K>
@@ -279,19 +341,30 @@ int launch_split(const fptc_batch &b, const fptc_codec &c, const Shape &sh, cons
   return (int)hipGetLastError();
 }
 
-template <int PREC>
+template <int PREC, bool MS>
 int launch_fused_t(const fptc_batch &b, const fptc_codec &c, const Shape &sh, const Plan &p, const float *gamma,
                    float *out, int32_t *status, void *stream) {
   static bool attr = false;
-  if (!attr && !(attr = set_lds_attr(k_fused256<PREC>))) return (int)hipErrorInvalidValue;
+  if (!attr && !(attr = set_lds_attr(k_fused256<PREC, MS>))) return (int)hipErrorInvalidValue;
   const int S = (c.E + 15) / 16;
-  const size_t lds = fused256_lds(Traits<PREC>::kBPieces, c, sh.wpc, sh.waves, c.n_rows);
+  const size_t lds = fused256_lds_ms(MS, Traits<PREC>::kBPieces, c.n_books, c.lmax, c.E, sh.wpc, sh.waves, c.n_rows);
   const int per_cu = (int)((160 * 1024) / lds);
   const int blocks = sh.blocks > 0 ? sh.blocks : device_cu_count() * (per_cu < 1 ? 1 : per_cu);
-  hipLaunchKernelGGL(k_fused256<PREC>, dim3(blocks), dim3(sh.waves * 64), lds, (hipStream_t)stream, b.words,
+  auto kern = k_fused256<PREC, MS>;
+  hipLaunchKernelGGL(kern, dim3(blocks), dim3(sh.waves * 64), lds, (hipStream_t)stream, b.words,
                      b.symlen, b.n_streams, c.E, S, c.lmax, c.n_books, c.n_rows, sh.wpc, c.lut, c.deq_val,
                      c.deq_zone, c.row_of_bin, c.basis, p.hdr, p.chunk_meta, gamma, out, status);
   return (int)hipGetLastError();
+}
+
+// Multi-symbol decode tables when they fit beside everything else.
+template <int PREC>
+int launch_fused_ms(const fptc_batch &b, const fptc_codec &c, const Shape &sh, const Plan &p, const float *gamma,
+                    float *out, int32_t *status, void *stream) {
+  if (fused256_lds_ms(true, Traits<PREC>::kBPieces, c.n_books, c.lmax, c.E, sh.wpc, sh.waves, c.n_rows) <=
+      160 * 1024)
+    return launch_fused_t<PREC, true>(b, c, sh, p, gamma, out, status, stream);
+  return launch_fused_t<PREC, false>(b, c, sh, p, gamma, out, status, stream);
 }
 
 }  // namespace
@@ -320,10 +393,10 @@ int launch_dqidct_mfma256(const fptc_batch &b, const fptc_codec &c, const Shape 
 int launch_fused256(const fptc_batch &b, const fptc_codec &c, const Shape &s, const Plan &p, const float *gamma,
                     int precision, float *out, int32_t *status, void *stream) {
   switch (precision) {
-    case FPTC_FP16: return launch_fused_t<FPTC_FP16>(b, c, s, p, gamma, out, status, stream);
-    case FPTC_FP16X2: return launch_fused_t<FPTC_FP16X2>(b, c, s, p, gamma, out, status, stream);
-    case FPTC_BF16: return launch_fused_t<FPTC_BF16>(b, c, s, p, gamma, out, status, stream);
-    case FPTC_BF16X3: return launch_fused_t<FPTC_BF16X3>(b, c, s, p, gamma, out, status, stream);
+    case FPTC_FP16: return launch_fused_ms<FPTC_FP16>(b, c, s, p, gamma, out, status, stream);
+    case FPTC_FP16X2: return launch_fused_ms<FPTC_FP16X2>(b, c, s, p, gamma, out, status, stream);
+    case FPTC_BF16: return launch_fused_ms<FPTC_BF16>(b, c, s, p, gamma, out, status, stream);
+    case FPTC_BF16X3: return launch_fused_ms<FPTC_BF16X3>(b, c, s, p, gamma, out, status, stream);
     default: return (int)hipErrorInvalidValue;
   }
 }

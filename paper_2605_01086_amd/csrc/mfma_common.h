@@ -100,6 +100,56 @@ __device__ inline bool dequant8(const uint8_t (&sy)[8], int k0, int E, bool vali
   return rest;
 }
 
+// Table of pre-split dequantized values for the unscaled path (at most two
+// pieces): one 32-bit entry per (book, row, symbol), the high piece in the
+// low half and the low piece in the high half, exactly what dequant8 would
+// produce for that symbol.
+template <int PREC>
+__device__ inline void stage_pieces(uint32_t *pq, const float *deq_val, int n, int tid, int nthreads) {
+  using T = Traits<PREC>;
+  constexpr int AP = T::kAPieces;
+  static_assert(AP <= 2, "pre-split table holds at most two pieces");
+  for (int i = tid; i < n; i += nthreads) {
+    uint16_t pc[AP];
+    split<T::kF16, AP>(deq_val[i], pc);
+    pq[i] = (uint32_t)pc[0] | (AP > 1 ? (uint32_t)pc[AP - 1] << 16 : 0u);
+  }
+}
+
+// Coefficient pieces of one k-step without per-stream scales: the 8 symbols
+// (s0, s1: byte j is bin k0 + j) looked up in the pre-split table of their
+// rows (pq: the book's table; rb: row of each bin when multi_row) and
+// repacked pairwise with byte permutes.  Returns whether any low piece is
+// nonzero.  Bins must lie inside [0, E) (E a multiple of 16).
+template <int PREC>
+__device__ inline bool gather8(uint32_t s0, uint32_t s1, int k0, const uint32_t *pq, bool multi_row,
+                               const uint8_t *rb, u8v (&a)[Traits<PREC>::kAPieces]) {
+  using T = Traits<PREC>;
+  constexpr int AP = T::kAPieces;
+  static_assert(AP <= 2, "pre-split table holds at most two pieces");
+  uint32_t t[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const uint32_t sym = ((j < 4 ? s0 : s1) >> (8 * (j & 3))) & 255u;
+    const uint32_t row = multi_row ? (uint32_t)rb[k0 + j] : 0u;
+    t[j] = pq[row * 256 + sym];
+  }
+  uint32_t hi[4], lo[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    hi[i] = __builtin_amdgcn_perm(t[2 * i + 1], t[2 * i], 0x05040100u);
+    lo[i] = __builtin_amdgcn_perm(t[2 * i + 1], t[2 * i], 0x07060302u);
+  }
+  typedef uint32_t u4v __attribute__((ext_vector_type(4)));
+  const u4v vh = {hi[0], hi[1], hi[2], hi[3]};
+  a[0] = __builtin_bit_cast(u8v, vh);
+  if constexpr (AP == 2) {
+    const u4v vl = {lo[0], lo[1], lo[2], lo[3]};
+    a[1] = __builtin_bit_cast(u8v, vl);
+  }
+  return AP > 1 && (((lo[0] | lo[1] | lo[2] | lo[3]) & 0x7fff7fffu) != 0);
+}
+
 // acc[t] += (basis rows of output tile t at this k-step) x (coefficient
 // pieces a), smallest terms first.  brow: this lane's basis row of tile 0 at
 // the k-step; tiles are tstride halves apart, pieces pstride halves apart.
@@ -150,6 +200,73 @@ __device__ inline void stage_basis(uint16_t *Bs, const float *basis, int N, int 
   }
 }
 
+// One 32-window tile of a wavefront: acc[t] (output rows t*32 ..) of this
+// lane's window from the window's symbols at sb[base + bin] in LDS.  k-steps
+// run from the highest bins down.  Without scales, with E a multiple of 16 and
+// at most two pieces, coefficients come from the pre-split table pq (two
+// k-steps in flight); otherwise through dequant8.  Lanes whose window is not
+// valid compute on the clamped window's symbols; only their lower-piece flag is
+// masked, so valid columns get exactly the general path's arithmetic.
+//   Bs: split basis [piece][n][RS]; rb/tv/tz/pq: this book's tables.
+template <int PREC, int NT>
+__device__ inline void tile_contract(f16v (&acc)[NT], const unsigned char *sb, int base, int h, int col, int S,
+                                     int E, bool valid, const uint16_t *Bs, int RS, const uint8_t *rb, const float *tv,
+                                     const uint8_t *tz, const uint32_t *pq, int n_rows, const float *gamma, float g0,
+                                     float g1, float g2) {
+  using T = Traits<PREC>;
+  constexpr int N = NT * 32;
+  constexpr int AP = T::kAPieces;
+  const int KH = S * 8;
+  const bool e_vec = (E % 16) == 0;
+#pragma unroll
+  for (int t = 0; t < NT; ++t)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[t][r] = 0.0f;
+  if constexpr (AP <= 2) {
+    if (!gamma && e_vec) {
+      const bool multi_row = n_rows > 1;
+      auto step = [&](int ss) {
+        const int k0 = h * KH + 8 * ss;
+        const uint2 u = *reinterpret_cast<const uint2 *>(sb + base + k0);
+        u8v a[AP];
+        const bool r = gather8<PREC>(u.x, u.y, k0, pq, multi_row, rb, a);
+        const bool any_rest = AP > 1 && __any(r && valid);
+        mfma_step<PREC, NT>(acc, a, Bs + col * RS + k0, 32 * RS, N * RS, any_rest);
+      };
+      // pairs of k-steps in one block so that the second step's reads
+      // overlap the first step's matrix ops; same order as one at a time
+      int ss = S - 1;
+      if (S & 1) step(ss--);
+#pragma unroll 1
+      for (; ss >= 1; ss -= 2) {
+        step(ss);
+        step(ss - 1);
+      }
+      return;
+    }
+  }
+#pragma unroll 1
+  for (int ss = S - 1; ss >= 0; --ss) {
+    const int k0 = h * KH + 8 * ss;
+    uint8_t sy[8];
+    if (e_vec) {  // the 8-bin group is inside [0, E) and 8-byte aligned
+      const uint2 u = *reinterpret_cast<const uint2 *>(sb + base + k0);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        sy[j] = (uint8_t)(u.x >> (8 * j));
+        sy[4 + j] = (uint8_t)(u.y >> (8 * j));
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < 8; ++j) sy[j] = sb[base + (k0 + j < E ? k0 + j : 0)];
+    }
+    u8v a[AP];
+    const bool r = dequant8<PREC>(sy, k0, E, valid, rb, tv, tz, gamma != nullptr, g0, g1, g2, a);
+    const bool any_rest = AP > 1 && __any(r);
+    mfma_step<PREC, NT>(acc, a, Bs + col * RS + k0, 32 * RS, N * RS, any_rest);
+  }
+}
+
 typedef float f4u __attribute__((ext_vector_type(4), aligned(4)));  // 16 bytes, 4-byte aligned
 
 // Store this lane's results of one 32x32 output block: rows n = nbase + 8 q +
@@ -169,6 +286,13 @@ __device__ inline void store_block(float *dst, const f16v &acc, int nbase, int h
         if (n0 + i < valid) dst[n0 + i] = v[i];
     }
   }
+}
+
+// Order a wavefront's LDS writes before its later LDS reads by other lanes.
+__device__ inline void wave_sync_lds() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 // Inclusive prefix sum across a 64-lane wavefront with DPP row shifts and row

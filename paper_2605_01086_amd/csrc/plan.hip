@@ -196,16 +196,16 @@ __global__ void __launch_bounds__(kScanThreads) k_plan_chunks(fptc_batch b, int 
     int tot;
     int64_t p = carry + block_excl_scan_dpp(sum, lds, tot);
     carry += tot;
+    // chunk m starts at symbol m * cb; walk the boundaries inside this
+    // thread's words from the first one at or after p
+    int64_t m = (p + cb - 1) / cb;
+    int64_t mb = m * cb;
 #pragma unroll
     for (int j = 0; j < kWordsPerThread; ++j) {
       const int c = cnt[j];
-      if (c > 0) {
-        // chunk starts m * cb with p <= m * cb < p + c
-        int64_t m = (p + cb - 1) / cb;
-        for (; m * cb < p + c && m < nc; ++m) {
-          meta[c0 + m].first_word = wb + j;
-          meta[c0 + m].first_sym = (int32_t)(p - m * cb);
-        }
+      for (; mb < p + c && m < nc; ++m, mb += cb) {
+        meta[c0 + m].first_word = wb + j;
+        meta[c0 + m].first_sym = (int32_t)(p - mb);
       }
       p += c;
     }
