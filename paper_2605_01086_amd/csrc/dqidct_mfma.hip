@@ -3,11 +3,11 @@
 //
 // For a tile of up to 32 consecutive windows of one stream (a chunk of the
 // plan, or a 32-window part of it) one wavefront forms
-//     D[n][w] = sum_k B[k][n] * c[w][k]
-// i.e. the transposed product basis^T x coefficients^T, with
-// v_mfma_f32_32x32x16_{f16,bf16}: FP32 accumulation, 16-bit operands.  The
-// transposed form leaves each lane holding four consecutive samples of one
-// window, so the result leaves as 16-byte stores straight from registers.
+//     D[w][n] = sum_k c[w][k] * B[k][n]
+// with v_mfma_f32_32x32x16_{f16,bf16} (coefficients as the A operand, basis
+// as B): FP32 accumulation, 16-bit operands.  A lane ends up holding one
+// sample of 16 windows, so every store instruction writes 32 consecutive
+// samples of two windows: whole 128-byte runs, the fewest write requests.
 //
 // Bins are mapped to MFMA k-slots so that each lane's coefficients are one
 // contiguous run of symbols: lane half h owns bins [h*Kp/2, (h+1)*Kp/2), k-step
@@ -187,12 +187,10 @@ __global__ void __launch_bounds__(kThreads, NT >= 4 ? 2 : (NT == 2 ? 3 : 4)) k_d
                               Tv + book * n_rows * 256, Tz + book * n_rows * 256, Pq + book * n_rows * 256, n_rows,
                               gamma, g0, g1, g2);
       if (tt == 0) settle_tile_syms(nx);  // before this chunk's stores
-      // lane holds rows n = t*32 + 8*q + 4*h + (0..3) of its window
-      if (valid > 0) {
-        float *dst = out + cm.out_base + (int64_t)wr * N;
+      float *win0 = out + cm.out_base + (int64_t)tt * kTileWindows * N;
+      const int rem = cm.out_len - tt * kTileWindows * N;
 #pragma unroll
-        for (int t = 0; t < NT; ++t) store_block(dst, acc[t], t * 32, h, valid, oscale);
-      }
+      for (int t = 0; t < NT; ++t) store_rows(win0, N, acc[t], t, h, col, rem, oscale);
       wave_sync_lds();
     }
     settle_tile_syms(nx);

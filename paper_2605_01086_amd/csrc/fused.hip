@@ -14,7 +14,7 @@
 //  2. per 32 windows: dequantize from LDS into split 16-bit operands, contract
 //     with the split IDCT basis on v_mfma_f32_32x32x16 (exactly the arithmetic
 //     of the stand-alone MFMA kernel, so results are bit-identical) and store
-//     each lane's four consecutive samples with one 16-byte write.
+//     rows of 32 consecutive samples per half-wave.
 #include <hip/hip_runtime.h>
 
 #include "fptc_internal.h"
@@ -161,13 +161,11 @@ __global__ void __launch_bounds__(64 * max_fused_waves(NT * 32)) k_fused(const u
         tile_contract<PREC, NT>(acc, sb, base, h, col, S, E, valid > 0, Bs, RS, Rb + book * E,
                                 Tv + book * n_rows * 256, Tz + book * n_rows * 256, Pq + book * n_rows * 256, n_rows,
                                 gamma, g0, g1, g2);
-        // this lane's window starts at out_base + wr * N; all windows of a
-        // chunk are consecutive in one stream
-        if (valid > 0) {
-          float *dst = out + cm.out_base + (int64_t)wr * N;
+        // the chunk's windows are consecutive in one stream
+        float *win0 = out + cm.out_base + (int64_t)tt * kTileWindows * N;
+        const int rem = cm.out_len - tt * kTileWindows * N;
 #pragma unroll
-          for (int t = 0; t < NT; ++t) store_block(dst, acc[t], t * 32, h, valid, oscale);
-        }
+        for (int t = 0; t < NT; ++t) store_rows(win0, N, acc[t], t, h, col, rem, oscale);
       }
       wave_sync_lds();
     }

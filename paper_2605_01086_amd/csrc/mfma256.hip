@@ -156,9 +156,19 @@ __global__ void __launch_bounds__(kMaxWaves256 * 64) k_dqidct_mfma256(fptc_batch
       contract_block256<PREC>(acc, Bb, blk * kSB, s1, KH, h, col, E, valid > 0, Rb + book * E,
                               Tv + book * n_rows * 256, Tz + book * n_rows * 256, gamma != nullptr, g0, g1, g2, sym);
     }
-    if (valid > 0) {
+    // the tile's windows may belong to different streams: each lane takes the
+    // output offset and length of the windows it holds from their own lanes
+    const int ob_lo = (int)(uint32_t)obase, ob_hi = (int)(obase >> 32);
 #pragma unroll
-      for (int t = 0; t < NT256; ++t) store_block(out + obase, acc[t], t * 32, h, valid, oscale);
+    for (int r = 0; r < 16; ++r) {
+      const int w = acc_window(r, h);
+      const int v_w = __shfl(valid, w);
+      const int64_t ob_w = ((int64_t)__shfl(ob_hi, w) << 32) | (int64_t)(uint32_t)__shfl(ob_lo, w);
+#pragma unroll
+      for (int t = 0; t < NT256; ++t) {
+        const int n = 32 * t + col;
+        if (n < v_w) out[ob_w + n] = acc[t][r] * oscale;
+      }
     }
   }
 }
@@ -298,11 +308,10 @@ __global__ void __launch_bounds__(kMaxWaves256 * 64) k_fused256(const uint64_t *
                                   Rb + book * E, Tv + book * n_rows * 256, Tz + book * n_rows * 256,
                                   gamma != nullptr, g0, g1, g2, sym);
       }
-      if (valid > 0) {
-        float *dst = out + cm.out_base + (int64_t)wr * N256;
+      float *win0 = out + cm.out_base + (int64_t)tt * kTileWindows * N256;
+      const int rem = tile_active ? cm.out_len - tt * kTileWindows * N256 : 0;
 #pragma unroll
-        for (int t = 0; t < NT256; ++t) store_block(dst, acc[t], t * 32, h, valid, oscale);
-      }
+      for (int t = 0; t < NT256; ++t) store_rows(win0, N256, acc[t], t, h, col, rem, oscale);
     }
     wave_sync_lds();
     cm = nm;

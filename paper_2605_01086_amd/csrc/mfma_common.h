@@ -56,15 +56,24 @@ __device__ inline void split(float x, uint16_t *out) {
   }
 }
 
+// acc[w][n] += sum over the k-step of coef[w][k] * basis[k][n] for a 32-window
+// by 32-sample block.  A operand = coefficients (lane l: window l % 32, bins
+// of k-slots 8 (l / 32) + j), B operand = basis (lane l: sample l % 32, same
+// k-slots).  The result leaves lane l with sample l % 32 of the windows
+// acc_window(r, l / 32), r = 0 .. 15, so that a store of one accumulator
+// element writes 32 consecutive samples of each of two windows.
 template <bool F16>
-__device__ inline f16v mfma(u8v a, u8v b, f16v acc) {
-  // a: 8 basis values (rows n), b: 8 coefficient values (columns w)
+__device__ inline f16v mfma(u8v basis, u8v coef, f16v acc) {
   if constexpr (F16)
-    return __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(h8, a), __builtin_bit_cast(h8, b), acc, 0, 0, 0);
+    return __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(h8, coef), __builtin_bit_cast(h8, basis), acc, 0,
+                                                  0, 0);
   else
-    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(b8, a), __builtin_bit_cast(b8, b), acc, 0, 0,
-                                                   0);
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(b8, coef), __builtin_bit_cast(b8, basis), acc,
+                                                   0, 0, 0);
 }
+
+// Window (row of the 32 x 32 block) of accumulator element r in lane half h.
+__device__ inline int acc_window(int r, int h) { return 8 * (r >> 2) + 4 * h + (r & 3); }
 
 // Dequantize the 8 coefficients of one k-step (bins k0 + j, symbols sy) and
 // split each into the precision's 16-bit pieces a[p].  Returns whether any
@@ -267,24 +276,20 @@ __device__ inline void tile_contract(f16v (&acc)[NT], const unsigned char *sb, i
   }
 }
 
-typedef float f4u __attribute__((ext_vector_type(4), aligned(4)));  // 16 bytes, 4-byte aligned
-
-// Store this lane's results of one 32x32 output block: rows n = nbase + 8 q +
-// 4 h + (0..3) of its window, whose samples start at dst; only the first
-// `valid` samples of the window exist.  Four consecutive samples leave as one
-// 16-byte store (global memory takes them at 4-byte alignment on gfx950).
-__device__ inline void store_block(float *dst, const f16v &acc, int nbase, int h, int valid, float scale) {
+// Store output tile t (samples 32 t .. 32 t + 31 of every window) of a block
+// of up to 32 consecutive windows of one stream: win0 = first sample of the
+// block's window 0, rem = samples from there to the end of the block (window
+// w holds samples [w N, w N + N) of it).  Lane (col, h) writes sample 32 t +
+// col of its 16 windows; each instruction covers two 128-byte runs.
+__device__ inline void store_rows(float *win0, int N, const f16v &acc, int t, int h, int col, int rem, float scale) {
+  // offset of element r = lane part (window 4 h, sample 32 t + col) + a part
+  // common to the wave, so each bound check is one compare with a scalar
+  const int lane_off = 4 * h * N + 32 * t + col;
+  float *p = win0 + lane_off;
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int n0 = nbase + 8 * q + 4 * h;
-    const f4u v = {acc[4 * q] * scale, acc[4 * q + 1] * scale, acc[4 * q + 2] * scale, acc[4 * q + 3] * scale};
-    if (n0 + 4 <= valid) {
-      *reinterpret_cast<f4u *>(dst + n0) = v;
-    } else {
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-        if (n0 + i < valid) dst[n0 + i] = v[i];
-    }
+  for (int r = 0; r < 16; ++r) {
+    const int c = acc_window(r, 0) * N;
+    if (lane_off < rem - c) p[c] = acc[r] * scale;
   }
 }
 
