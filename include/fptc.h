@@ -115,9 +115,10 @@ typedef struct {
 /* Launch shape.  Zero fields take the library defaults. */
 typedef struct {
   int32_t windows_per_chunk;  /* windows per decode work item (chunk); default 32 */
-  int32_t waves_per_block;    /* 0: default (4; fptc_decompress_batch: the most, up to 16,
-                                 8 at N >= 128, whose LDS fits); at most 16 (fused: 8 at
-                                 N >= 128, else FPTC_ERR_UNSUPPORTED) */
+  int32_t waves_per_block;    /* 0: default (4; fptc_decode_batch: the most, up to 16, whose
+                                 LDS fits; fptc_decompress_batch: the same, up to 8 at
+                                 N >= 128); at most 16 (fused: 8 at N >= 128, else
+                                 FPTC_ERR_UNSUPPORTED) */
   int32_t blocks;             /* persistent grid size; default: enough to fill the GPU */
   int32_t reserved0;
 } fptc_launch;

@@ -59,6 +59,17 @@ Layout layout_for(const fptc_batch *b, const fptc_codec *c, const Shape &s) {
   off = align256(off + (n + 1) * sizeof(int64_t));
   L.chunk_off = off;
   off = align256(off + (n + 1) * sizeof(int64_t));
+  L.seg_off = off;
+  off = align256(off + (n + 1) * sizeof(int64_t));
+  // a stream's 4096-word segments start at its first word aligned down to 16:
+  // with disjoint word ranges at most (n_words + 16 n) / 4096 + n in all
+  L.seg_cap = (b->n_words + 16 * n) / 4096 + n + 1;
+  L.seg_stream = off;
+  off = align256(off + L.seg_cap * sizeof(int32_t));
+  L.seg_sum = off;
+  off = align256(off + L.seg_cap * sizeof(int32_t));
+  L.seg_base = off;
+  off = align256(off + L.seg_cap * sizeof(int64_t));
   L.bwd_part = off;
   off = align256(off + L.chunk_cap * 3 * sizeof(double));
   L.tile_cap = (max_windows + kTileWindows - 1) / kTileWindows + 1;
@@ -79,8 +90,13 @@ Plan plan_view(void *ws, const Layout &L) {
   v.bwd_part = reinterpret_cast<double *>(p + L.bwd_part);
   v.tile_stream = reinterpret_cast<int32_t *>(p + L.tile_stream);
   v.chunk_meta = reinterpret_cast<ChunkMeta *>(p + L.chunk_meta);
+  v.seg_off = reinterpret_cast<int64_t *>(p + L.seg_off);
+  v.seg_stream = reinterpret_cast<int32_t *>(p + L.seg_stream);
+  v.seg_sum = reinterpret_cast<int32_t *>(p + L.seg_sum);
+  v.seg_base = reinterpret_cast<int64_t *>(p + L.seg_base);
   v.chunk_cap = L.chunk_cap;
   v.tile_cap = L.tile_cap;
+  v.seg_cap = L.seg_cap;
   return v;
 }
 
@@ -130,6 +146,10 @@ int32_t fptc_decode_batch(const fptc_batch *batch, const fptc_codec *codec, cons
   int rc;
   if ((rc = check_batch(batch)) || (rc = check_codec(codec)) || (rc = resolve_shape(launch, codec, &s))) return rc;
   if (!ws || (!symbols_out && batch->n_symbols > 0)) return FPTC_ERR_INVALID_ARG;
+  if (s.auto_waves) {  // the most waves (up to 16) whose symbol buffers fit in LDS
+    s.waves = 16;
+    while (s.waves > 1 && decode_lds_bytes(*codec, s) > 160 * 1024) --s.waves;
+  }
   if (decode_lds_bytes(*codec, s) > 160 * 1024) return FPTC_ERR_UNSUPPORTED;
   Layout L = layout_for(batch, codec, s);
   if (ws_bytes < L.total) return FPTC_ERR_WORKSPACE;

@@ -20,7 +20,7 @@ constexpr int kTileWindows = 32;  // windows per MFMA tile (one 32x32 output blo
 // Everything a wavefront needs to decode one chunk, written by the plan.
 struct ChunkMeta {
   int64_t first_word;  // global index of the first word holding a symbol of the chunk; -1 = skip
-  int64_t word_end;    // end of the stream's words
+  int64_t word_end;    // end (exclusive) of the chunk's words
   int64_t sym_base;    // global index of the chunk's first decoded symbol
   int64_t out_base;    // global index of the chunk's first output sample
   int32_t first_sym;   // chunk-relative index of the first word's first symbol (<= 0)
@@ -48,8 +48,8 @@ struct Shape {
 //   tile_stream int32[tcap] stream owning the first window of each 32-window tile
 //   chunk_meta ChunkMeta[cap] per-chunk decode record
 struct Layout {
-  size_t hdr, win_off, chunk_off, bwd_part, tile_stream, chunk_meta, total;
-  int64_t chunk_cap, tile_cap;
+  size_t hdr, win_off, chunk_off, seg_off, bwd_part, tile_stream, seg_stream, seg_sum, seg_base, chunk_meta, total;
+  int64_t chunk_cap, tile_cap, seg_cap;
 };
 
 Layout layout_for(const fptc_batch *b, const fptc_codec *c, const Shape &s);
@@ -61,8 +61,12 @@ struct Plan {
   int64_t *chunk_off;
   double *bwd_part;
   int32_t *tile_stream;
+  int64_t *seg_off;     // [n_streams + 1] symlen segments per stream, prefix
+  int32_t *seg_stream;  // [seg_cap] stream of each segment
+  int32_t *seg_sum;     // [seg_cap] symbols in each segment
+  int64_t *seg_base;    // [seg_cap] symbols of the stream before each segment
   ChunkMeta *chunk_meta;
-  int64_t chunk_cap, tile_cap;
+  int64_t chunk_cap, tile_cap, seg_cap;
 };
 
 Plan plan_view(void *ws, const Layout &L);

@@ -35,7 +35,7 @@ __device__ inline void stage_basis_block(uint16_t *Bb, const float *basis, int E
   const float bscale = T::kF16 ? kBasisScaleF16 : 1.0f;
   constexpr int W = 16 * kSB;
   for (int i = tid; i < N256 * W; i += nthreads) {
-    const int n = i / W, r = i % W;
+    const int n = i % N256, r = i / N256;  // consecutive threads read consecutive n of one basis row
     const int h = r / (8 * kSB), o = r % (8 * kSB);
     const int k = h * KH + 8 * s0 + o;
     const float v = k < E ? basis[(int64_t)k * N256 + n] * bscale : 0.0f;

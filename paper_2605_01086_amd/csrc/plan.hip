@@ -1,9 +1,10 @@
 // Batch planning kernels (stream/chunk setup and the symlen prefix sums).
 //
 // Section 4.2 places each word's decoded symbols by an exclusive prefix sum of
-// the per-word symbol counts.  Here the sum is taken per stream, and only the
-// words where a chunk of `wpc` windows begins are recorded: a chunk then
-// decodes from that word on its own, with no cross-chunk dependency.
+// the per-word symbol counts.  Here the sum is taken per stream, in two levels
+// (4096-word segments, then the segments of each stream), and only the words
+// where a chunk of `wpc` windows begins are recorded: a chunk then decodes
+// from that word on its own, with no cross-chunk dependency.
 #include <hip/hip_runtime.h>
 
 #include "fptc_internal.h"
@@ -14,7 +15,8 @@ namespace {
 
 constexpr int kPlanThreads = 1024;
 constexpr int kScanThreads = 256;
-constexpr int kWordsPerThread = 16;  // one 16-byte symlen load per thread and iteration
+constexpr int kWordsPerThread = 16;  // one 16-byte symlen load per thread
+constexpr int64_t kSegWords = (int64_t)kScanThreads * kWordsPerThread;  // words per segment
 
 // Inclusive scan across one 64-lane wavefront.
 template <typename T>
@@ -49,22 +51,26 @@ __device__ inline T block_excl_scan(T v, T *lds, T &total) {
   return r;
 }
 
-// One workgroup: per-stream window counts and chunk counts, their exclusive
-// prefix sums, and header validation.
+// One workgroup: per-stream window, chunk and symlen-segment counts, their
+// exclusive prefix sums, header validation, and the segment -> stream map.
+// Segments are kSegWords words on a 16-word grid aligned down from the
+// stream's first word.
 __global__ void __launch_bounds__(kPlanThreads) k_plan_streams(fptc_batch b, int N, int E, int wpc,
                                                                int64_t *hdr, int64_t *win_off, int64_t *chunk_off,
-                                                               int32_t *status) {
+                                                               int64_t *seg_off, int32_t *seg_stream,
+                                                               int64_t seg_cap, int32_t *status) {
   __shared__ int64_t lds[kPlanThreads / kWave + 1];
   const int n = b.n_streams;
   const int64_t win_cap = b.n_symbols / E;
-  int64_t carry_w = 0, carry_c = 0;
+  int64_t carry_w = 0, carry_c = 0, carry_g = 0;
   for (int base = 0; base < n; base += kPlanThreads) {
     const int s = base + threadIdx.x;
-    int64_t nw = 0;
+    int64_t nw = 0, w0 = 0, w1 = 0;
     int flag = 0;
     if (s < n) {
       const int64_t s0 = b.sample_off[s], s1 = b.sample_off[s + 1];
-      const int64_t w0 = b.word_off[s], w1 = b.word_off[s + 1];
+      w0 = b.word_off[s];
+      w1 = b.word_off[s + 1];
       if (s0 < 0 || s1 < s0 || s1 > b.n_samples || w0 < 0 || w1 < w0 || w1 > b.n_words) flag = FPTC_STREAM_BAD_HEADER;
       else nw = (s1 - s0 + N - 1) / N;
     }
@@ -75,17 +81,26 @@ __global__ void __launch_bounds__(kPlanThreads) k_plan_streams(fptc_batch b, int
     const int64_t nc = flag ? 0 : (nw + wpc - 1) / wpc;
     const int64_t co = carry_c + block_excl_scan<int64_t, kPlanThreads>(nc, lds, tot);
     carry_c += tot;
+    const int64_t a0 = w0 & ~(int64_t)15;
+    const int64_t ng = (flag || nc == 0 || w1 <= w0) ? 0 : (w1 - a0 + kSegWords - 1) / kSegWords;
+    const int64_t go = carry_g + block_excl_scan<int64_t, kPlanThreads>(ng, lds, tot);
+    carry_g += tot;
     if (s < n) {
       win_off[s] = wo;
       chunk_off[s] = co;
+      seg_off[s] = go;
       if (status) status[s] = flag;
+      for (int64_t g = go; g < go + ng && g < seg_cap; ++g) seg_stream[g] = s;
     }
   }
   if (threadIdx.x == 0) {
     win_off[n] = carry_w;
     chunk_off[n] = carry_c;
+    seg_off[n] = carry_g;
     hdr[0] = carry_c;
     hdr[1] = carry_w < win_cap ? carry_w : win_cap;
+    hdr[2] = carry_g < seg_cap ? carry_g : seg_cap;
+    hdr[3] = seg_cap;
   }
 }
 
@@ -109,17 +124,77 @@ __device__ inline int block_excl_scan_dpp(int v, int *lds, int &total) {
   return before + incl - v;
 }
 
-// One workgroup per stream: exclusive scan of the stream's symlen; every word
-// whose symbol range [p, p + symlen) contains the first symbol of a chunk
-// (a multiple of wpc * E) is recorded in that chunk's record.  Also writes the
-// per-chunk records, the 32-window tile owners, and checks the symbol total
-// and the symlen bound.  4096 words per iteration, 16 per thread, the next
-// iteration's bytes loaded while the current ones are scanned.
-__global__ void __launch_bounds__(kScanThreads) k_plan_chunks(fptc_batch b, int N, int E, int wpc,
-                                                              const int64_t *win_off, const int64_t *chunk_off,
-                                                              int32_t *tile_stream, int64_t tile_cap,
-                                                              ChunkMeta *meta, int32_t *status) {
+// The words of one segment: this thread's 16 symlen bytes (words outside the
+// stream read as 0), each clamped to 64 with the clamp reported.
+struct SegWords {
+  int64_t first;  // global index of this thread's first word
+  int cnt[kWordsPerThread];
+};
+
+__device__ inline int load_seg_words(const fptc_batch &b, int64_t g, const int64_t *seg_off,
+                                     const int32_t *seg_stream, int s, SegWords &sw) {
+  const int64_t w0 = b.word_off[s], w1 = b.word_off[s + 1];
+  const int64_t a0 = w0 & ~(int64_t)15;
+  const int64_t first = a0 + (g - seg_off[s]) * kSegWords + (int64_t)threadIdx.x * kWordsPerThread;
+  sw.first = first;
+  uint8_t c[kWordsPerThread];
+  if ((reinterpret_cast<uintptr_t>(b.symlen) & 15) == 0 && first >= w0 && first + kWordsPerThread <= w1) {
+    const uint4 u = *reinterpret_cast<const uint4 *>(b.symlen + first);
+    const uint32_t x[4] = {u.x, u.y, u.z, u.w};
+#pragma unroll
+    for (int j = 0; j < kWordsPerThread; ++j) c[j] = (uint8_t)(x[j >> 2] >> (8 * (j & 3)));
+  } else {
+#pragma unroll
+    for (int j = 0; j < kWordsPerThread; ++j) {
+      const int64_t w = first + j;
+      c[j] = (w >= w0 && w < w1) ? b.symlen[w] : (uint8_t)0;
+    }
+  }
+  int bad = 0;
+#pragma unroll
+  for (int j = 0; j < kWordsPerThread; ++j) {
+    int v = c[j];
+    if (v > 64) {
+      bad = FPTC_STREAM_BAD_SYMLEN;
+      v = 64;
+    }
+    sw.cnt[j] = v;
+  }
+  return bad;
+}
+
+// One workgroup per segment: the segment's symbol count (symlen clamped to
+// 64; a larger symlen is flagged).
+__global__ void __launch_bounds__(kScanThreads) k_plan_seg_sums(fptc_batch b, const int64_t *hdr,
+                                                                const int64_t *seg_off, const int32_t *seg_stream,
+                                                                int32_t *seg_sum, int32_t *status) {
   __shared__ int lds[kScanThreads / kWave];
+  const int64_t g = blockIdx.x;
+  if (g >= hdr[2]) return;
+  const int s = seg_stream[g];
+  if (seg_off[s + 1] > hdr[3]) return;  // the stream's segments did not fit (flagged)
+  SegWords sw;
+  const int bad = load_seg_words(b, g, seg_off, seg_stream, s, sw);
+  int sum = 0;
+#pragma unroll
+  for (int j = 0; j < kWordsPerThread; ++j) sum += sw.cnt[j];
+  int tot;
+  block_excl_scan_dpp(sum, lds, tot);
+  if (threadIdx.x == 0) seg_sum[g] = tot;
+  if (bad && status) atomicOr(&status[s], bad);
+}
+
+// One workgroup per stream: exclusive scan of its segment sums (symbols of
+// the stream before each segment), the symbol-count check, the chunk
+// records' fixed fields, and the 32-window tile owners.
+__global__ void __launch_bounds__(kScanThreads) k_plan_stream_scan(fptc_batch b, int N, int E, int wpc,
+                                                                   const int64_t *win_off, const int64_t *chunk_off,
+                                                                   const int64_t *seg_off, int64_t seg_cap,
+                                                                   const int32_t *seg_sum, int64_t *seg_base,
+                                                                   int32_t *tile_stream,
+                                                                   int64_t tile_cap, ChunkMeta *meta,
+                                                                   int32_t *status) {
+  __shared__ int64_t lds[kScanThreads / kWave + 1];
   const int s = blockIdx.x;
   // Every stream, valid or not, records itself as the owner of the 32-window
   // tiles whose first window it holds, so a tile's first stream is one load.
@@ -130,9 +205,8 @@ __global__ void __launch_bounds__(kScanThreads) k_plan_chunks(fptc_batch b, int 
   }
   const int64_t c0 = chunk_off[s], nc = chunk_off[s + 1] - c0;
   if (nc <= 0) return;  // empty stream or bad header (then status already flagged)
-  const int64_t w0 = b.word_off[s], w1 = b.word_off[s + 1];
+  const int64_t w1 = b.word_off[s + 1];
   const int64_t nw = win_off[s + 1] - win_off[s];
-  const int64_t cb = (int64_t)wpc * E;  // symbols per chunk
   {
     const int64_t so = b.sample_off[s], L = b.sample_off[s + 1] - so;
     const int bk = b.book_id ? (int)b.book_id[s] : 0;
@@ -154,64 +228,61 @@ __global__ void __launch_bounds__(kScanThreads) k_plan_chunks(fptc_batch b, int 
       meta[c0 + i] = cm;
     }
   }
-  __syncthreads();
-
-  // iterate over 16-byte aligned groups of symlen bytes covering [w0, w1)
-  const bool vec = (reinterpret_cast<uintptr_t>(b.symlen) & 15) == 0;
-  const int64_t base0 = vec ? (w0 & ~(int64_t)15) : w0;
-  constexpr int kIter = kScanThreads * kWordsPerThread;
-  auto load16 = [&](int64_t first, uint8_t (&c)[kWordsPerThread]) {
-    if (vec && first >= w0 && first + kWordsPerThread <= w1) {
-      const uint4 u = *reinterpret_cast<const uint4 *>(b.symlen + first);
-      const uint32_t x[4] = {u.x, u.y, u.z, u.w};
-#pragma unroll
-      for (int j = 0; j < kWordsPerThread; ++j) c[j] = (uint8_t)(x[j >> 2] >> (8 * (j & 3)));
-    } else {
-#pragma unroll
-      for (int j = 0; j < kWordsPerThread; ++j) {
-        const int64_t w = first + j;
-        c[j] = (w >= w0 && w < w1) ? b.symlen[w] : (uint8_t)0;
-      }
-    }
-  };
-  int64_t carry = 0;
-  int bad = 0;
-  uint8_t nxt[kWordsPerThread];
-  load16(base0 + (int64_t)threadIdx.x * kWordsPerThread, nxt);
-  for (int64_t base = base0; base < w1; base += kIter) {
-    const int64_t wb = base + (int64_t)threadIdx.x * kWordsPerThread;
-    int cnt[kWordsPerThread];
-    int sum = 0;
-#pragma unroll
-    for (int j = 0; j < kWordsPerThread; ++j) {
-      int c = nxt[j];
-      if (c > 64) {
-        bad |= FPTC_STREAM_BAD_SYMLEN;
-        c = 64;
-      }
-      cnt[j] = c;
-      sum += c;
-    }
-    if (base + kIter < w1) load16(wb + kIter, nxt);
-    int tot;
-    int64_t p = carry + block_excl_scan_dpp(sum, lds, tot);
-    carry += tot;
-    // chunk m starts at symbol m * cb; walk the boundaries inside this
-    // thread's words from the first one at or after p
-    int64_t m = (p + cb - 1) / cb;
-    int64_t mb = m * cb;
-#pragma unroll
-    for (int j = 0; j < kWordsPerThread; ++j) {
-      const int c = cnt[j];
-      for (; mb < p + c && m < nc; ++m, mb += cb) {
-        meta[c0 + m].first_word = wb + j;
-        meta[c0 + m].first_sym = (int32_t)(p - mb);
-      }
-      p += c;
-    }
+  const int64_t g0 = seg_off[s], ng = seg_off[s + 1] - g0;
+  if (seg_off[s + 1] > seg_cap) {  // word ranges of streams overlap: no segment room
+    if (threadIdx.x == 0 && status) atomicOr(&status[s], FPTC_STREAM_BAD_HEADER);
+    return;  // its chunks keep first_word = -1
   }
-  if (threadIdx.x == 0 && carry != nw * E) bad |= FPTC_STREAM_BAD_COUNT;
-  if (bad && status) atomicOr(&status[s], bad);
+  int64_t carry = 0;
+  for (int64_t base = 0; base < ng; base += kScanThreads) {
+    const int64_t i = base + threadIdx.x;
+    const int64_t v = i < ng ? seg_sum[g0 + i] : 0;
+    int64_t tot;
+    const int64_t ex = block_excl_scan<int64_t, kScanThreads>(v, lds, tot);
+    if (i < ng) seg_base[g0 + i] = carry + ex;
+    carry += tot;
+  }
+  if (threadIdx.x == 0 && carry != nw * E && status) atomicOr(&status[s], FPTC_STREAM_BAD_COUNT);
+}
+
+// One workgroup per segment: exclusive scan of its words' symlen on top of
+// the segment's base; every word whose symbol range [p, p + symlen) holds the
+// first symbol of a chunk (a multiple of wpc * E) becomes that chunk's first
+// word, and the chunk before it ends at that word (inclusive when the chunk
+// starts inside the word).
+__global__ void __launch_bounds__(kScanThreads) k_plan_seg_chunks(fptc_batch b, int E, int wpc, const int64_t *hdr,
+                                                                  const int64_t *chunk_off, const int64_t *seg_off,
+                                                                  const int32_t *seg_stream,
+                                                                  const int64_t *seg_base, ChunkMeta *meta) {
+  __shared__ int lds[kScanThreads / kWave];
+  const int64_t g = blockIdx.x;
+  if (g >= hdr[2]) return;
+  const int s = seg_stream[g];
+  if (seg_off[s + 1] > hdr[3]) return;  // the stream's segments did not fit (flagged)
+  SegWords sw;
+  load_seg_words(b, g, seg_off, seg_stream, s, sw);
+  int sum = 0;
+#pragma unroll
+  for (int j = 0; j < kWordsPerThread; ++j) sum += sw.cnt[j];
+  int tot;
+  const int ex = block_excl_scan_dpp(sum, lds, tot);
+  const int64_t c0 = chunk_off[s], nc = chunk_off[s + 1] - c0;
+  const int64_t cb = (int64_t)wpc * E;  // symbols per chunk
+  int64_t p = seg_base[g] + ex;
+  // the boundaries inside this thread's words, from the first at or after p
+  int64_t m = (p + cb - 1) / cb;
+  int64_t mb = m * cb;
+#pragma unroll
+  for (int j = 0; j < kWordsPerThread; ++j) {
+    const int c = sw.cnt[j];
+    for (; mb < p + c && m < nc; ++m, mb += cb) {
+      const int64_t w = sw.first + j;
+      meta[c0 + m].first_word = w;
+      meta[c0 + m].first_sym = (int32_t)(p - mb);
+      if (m > 0) meta[c0 + m - 1].word_end = p == mb ? w : w + 1;
+    }
+    p += c;
+  }
 }
 
 }  // namespace
@@ -220,11 +291,19 @@ int launch_plan(const fptc_batch &b, const fptc_codec &c, const Shape &s, const 
                 void *stream) {
   hipStream_t st = (hipStream_t)stream;
   hipLaunchKernelGGL(k_plan_streams, dim3(1), dim3(kPlanThreads), 0, st, b, c.N, c.E, s.wpc, p.hdr, p.win_off,
-                     p.chunk_off, status);
+                     p.chunk_off, p.seg_off, p.seg_stream, p.seg_cap, status);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return (int)e;
-  hipLaunchKernelGGL(k_plan_chunks, dim3(b.n_streams), dim3(kScanThreads), 0, st, b, c.N, c.E, s.wpc, p.win_off,
-                     p.chunk_off, p.tile_stream, p.tile_cap, p.chunk_meta, status);
+  const unsigned nseg = (unsigned)(p.seg_cap > 0 ? p.seg_cap : 1);  // blocks past hdr[2] exit at once
+  hipLaunchKernelGGL(k_plan_seg_sums, dim3(nseg), dim3(kScanThreads), 0, st, b, p.hdr, p.seg_off, p.seg_stream,
+                     p.seg_sum, status);
+  if ((e = hipGetLastError()) != hipSuccess) return (int)e;
+  hipLaunchKernelGGL(k_plan_stream_scan, dim3(b.n_streams), dim3(kScanThreads), 0, st, b, c.N, c.E, s.wpc,
+                     p.win_off, p.chunk_off, p.seg_off, p.seg_cap, p.seg_sum, p.seg_base, p.tile_stream, p.tile_cap,
+                     p.chunk_meta, status);
+  if ((e = hipGetLastError()) != hipSuccess) return (int)e;
+  hipLaunchKernelGGL(k_plan_seg_chunks, dim3(nseg), dim3(kScanThreads), 0, st, b, c.E, s.wpc, p.hdr, p.chunk_off,
+                     p.seg_off, p.seg_stream, p.seg_base, p.chunk_meta);
   return (int)hipGetLastError();
 }
 
