@@ -77,6 +77,8 @@ Layout layout_for(const fptc_batch *b, const fptc_codec *c, const Shape &s) {
   off = align256(off + L.tile_cap * sizeof(int32_t));
   L.chunk_meta = off;
   off = align256(off + L.chunk_cap * sizeof(ChunkMeta));
+  L.basis_split = off;
+  off = align256(off + basis_split256_bytes(c->N));
   L.total = off;
   return L;
 }
@@ -94,6 +96,7 @@ Plan plan_view(void *ws, const Layout &L) {
   v.seg_stream = reinterpret_cast<int32_t *>(p + L.seg_stream);
   v.seg_sum = reinterpret_cast<int32_t *>(p + L.seg_sum);
   v.seg_base = reinterpret_cast<int64_t *>(p + L.seg_base);
+  v.basis_split = reinterpret_cast<uint16_t *>(p + L.basis_split);
   v.chunk_cap = L.chunk_cap;
   v.tile_cap = L.tile_cap;
   v.seg_cap = L.seg_cap;

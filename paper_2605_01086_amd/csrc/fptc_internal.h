@@ -48,7 +48,8 @@ struct Shape {
 //   tile_stream int32[tcap] stream owning the first window of each 32-window tile
 //   chunk_meta ChunkMeta[cap] per-chunk decode record
 struct Layout {
-  size_t hdr, win_off, chunk_off, seg_off, bwd_part, tile_stream, seg_stream, seg_sum, seg_base, chunk_meta, total;
+  size_t hdr, win_off, chunk_off, seg_off, bwd_part, tile_stream, seg_stream, seg_sum, seg_base, chunk_meta,
+      basis_split, total;
   int64_t chunk_cap, tile_cap, seg_cap;
 };
 
@@ -66,6 +67,7 @@ struct Plan {
   int32_t *seg_sum;     // [seg_cap] symbols in each segment
   int64_t *seg_base;    // [seg_cap] symbols of the stream before each segment
   ChunkMeta *chunk_meta;
+  uint16_t *basis_split;  // window 256: the split basis in the LDS image of each staged block
   int64_t chunk_cap, tile_cap, seg_cap;
 };
 
@@ -89,6 +91,7 @@ int launch_fused(const fptc_batch &b, const fptc_codec &c, const Shape &s, const
                  int precision, float *out, int32_t *status, void *stream);
 
 bool mfma256_supported(int E, int precision);
+size_t basis_split256_bytes(int N);
 bool fused256_supported(const fptc_codec &c, int precision, int wpc, int waves);
 int launch_dqidct_mfma256(const fptc_batch &b, const fptc_codec &c, const Shape &s, const Plan &p,
                           const uint8_t *symbols, const float *gamma, int precision, float *out, void *stream);

@@ -46,6 +46,28 @@ __device__ inline void stage_basis_block(uint16_t *Bb, const float *basis, int E
   }
 }
 
+constexpr int kMaxBlocks256 = (N256 / 16 + kSB - 1) / kSB;  // staged blocks at E = 256
+
+// The split basis of every staged block, written once per call into the
+// workspace in the exact LDS image of the block, so that staging a block in
+// the main kernels is a plain 16-byte copy.  One workgroup per block.
+template <int PREC>
+__global__ void __launch_bounds__(256) k_split_basis256(const float *__restrict__ basis, int E, int KH,
+                                                        uint16_t *bsplit) {
+  using T = Traits<PREC>;
+  const int blk = blockIdx.x;
+  stage_basis_block<PREC>(bsplit + (size_t)blk * (block_basis_bytes(T::kBPieces) / 2), basis, E, KH, blk * kSB,
+                          threadIdx.x, blockDim.x);
+}
+
+// Copy one staged block (bytes a multiple of 16) from the workspace to LDS.
+__device__ inline void copy_basis_block(uint16_t *Bb, const uint16_t *__restrict__ src, int bytes, int tid,
+                                        int nthreads) {
+  const uint4 *s4 = reinterpret_cast<const uint4 *>(src);
+  uint4 *d4 = reinterpret_cast<uint4 *>(Bb);
+  for (int i = tid; i < bytes / 16; i += nthreads) d4[i] = s4[i];
+}
+
 // Contract k-steps [s0, s1) of one 32-window tile against the staged block;
 // symbols come from `sym(k0)`: the 8 symbols of bins k0 .. k0 + 7, byte j of
 // the pair being bin k0 + j.  (The pre-split table of the resident kernels
@@ -79,7 +101,8 @@ template <int PREC>
 __global__ void __launch_bounds__(kMaxWaves256 * 64) k_dqidct_mfma256(fptc_batch b, int E, int S, int n_books,
                                                                        int n_rows, const float *deq_val,
                                                                        const uint8_t *deq_zone,
-                                                                       const uint8_t *row_of_bin, const float *basis,
+                                                                       const uint8_t *row_of_bin,
+                                                                       const uint16_t *__restrict__ bsplit,
                                                                        const int64_t *hdr, const int64_t *win_off,
                                                                        const int32_t *tile_stream,
                                                                        const uint8_t *symbols, const float *__restrict__ gamma,
@@ -150,7 +173,8 @@ __global__ void __launch_bounds__(kMaxWaves256 * 64) k_dqidct_mfma256(fptc_batch
     };
     for (int blk = nblk - 1; blk >= 0; --blk) {
       __syncthreads();
-      stage_basis_block<PREC>(Bb, basis, E, KH, blk * kSB, threadIdx.x, nthreads);
+      copy_basis_block(Bb, bsplit + (size_t)blk * (block_basis_bytes(T::kBPieces) / 2),
+                       (int)block_basis_bytes(T::kBPieces), threadIdx.x, nthreads);
       __syncthreads();
       const int s1 = min(S, (blk + 1) * kSB);
       contract_block256<PREC>(acc, Bb, blk * kSB, s1, KH, h, col, E, valid > 0, Rb + book * E,
@@ -201,7 +225,7 @@ __global__ void __launch_bounds__(kMaxWaves256 * 64) k_fused256(const uint64_t *
                                                                  const float *__restrict__ deq_val,
                                                                  const uint8_t *__restrict__ deq_zone,
                                                                  const uint8_t *__restrict__ row_of_bin,
-                                                                 const float *__restrict__ basis,
+                                                                 const uint16_t *__restrict__ bsplit,
                                                                  const int64_t *__restrict__ hdr,
                                                                  const ChunkMeta *__restrict__ meta,
                                                                  const float *__restrict__ gamma, float *out,
@@ -301,7 +325,8 @@ __global__ void __launch_bounds__(kMaxWaves256 * 64) k_fused256(const uint64_t *
       };
       for (int blk = nblk - 1; blk >= 0; --blk) {
         __syncthreads();
-        stage_basis_block<PREC>(Bb, basis, E, KH, blk * kSB, threadIdx.x, nthreads);
+        copy_basis_block(Bb, bsplit + (size_t)blk * (block_basis_bytes(T::kBPieces) / 2),
+                       (int)block_basis_bytes(T::kBPieces), threadIdx.x, nthreads);
         __syncthreads();
         if (tile_active)
           contract_block256<PREC>(acc, Bb, blk * kSB, min(S, (blk + 1) * kSB), KH, h, col, E, valid > 0,
@@ -335,17 +360,28 @@ bool set_lds_attr(K kern) {
                              160 * 1024) == hipSuccess;
 }
 
+// Split the basis into the workspace (one workgroup per staged block).
+template <int PREC>
+int split_basis(const fptc_codec &c, int S, const Plan &p, void *stream) {
+  const int nblk = (S + kSB - 1) / kSB;
+  hipLaunchKernelGGL(k_split_basis256<PREC>, dim3(nblk), dim3(256), 0, (hipStream_t)stream, c.basis, c.E, S * 8,
+                     p.basis_split);
+  return (int)hipGetLastError();
+}
+
 template <int PREC>
 int launch_split(const fptc_batch &b, const fptc_codec &c, const Shape &sh, const Plan &p, const uint8_t *symbols,
                  const float *gamma, float *out, void *stream) {
   static bool attr = false;
   if (!attr && !(attr = set_lds_attr(k_dqidct_mfma256<PREC>))) return (int)hipErrorInvalidValue;
   const int S = (c.E + 15) / 16;
+  int rc = split_basis<PREC>(c, S, p, stream);
+  if (rc) return rc;
   const size_t lds = split256_lds(Traits<PREC>::kBPieces, c);
   const int per_cu = (int)((160 * 1024) / lds);
   const int blocks = sh.blocks > 0 ? sh.blocks : device_cu_count() * (per_cu < 1 ? 1 : per_cu);
   hipLaunchKernelGGL(k_dqidct_mfma256<PREC>, dim3(blocks), dim3(kMaxWaves256 * 64), lds, (hipStream_t)stream, b,
-                     c.E, S, c.n_books, c.n_rows, c.deq_val, c.deq_zone, c.row_of_bin, c.basis, p.hdr, p.win_off,
+                     c.E, S, c.n_books, c.n_rows, c.deq_val, c.deq_zone, c.row_of_bin, p.basis_split, p.hdr, p.win_off,
                      p.tile_stream, symbols, gamma, out);
   return (int)hipGetLastError();
 }
@@ -356,13 +392,15 @@ int launch_fused_t(const fptc_batch &b, const fptc_codec &c, const Shape &sh, co
   static bool attr = false;
   if (!attr && !(attr = set_lds_attr(k_fused256<PREC, MS>))) return (int)hipErrorInvalidValue;
   const int S = (c.E + 15) / 16;
+  int rc = split_basis<PREC>(c, S, p, stream);
+  if (rc) return rc;
   const size_t lds = fused256_lds_ms(MS, Traits<PREC>::kBPieces, c.n_books, c.lmax, c.E, sh.wpc, sh.waves, c.n_rows);
   const int per_cu = (int)((160 * 1024) / lds);
   const int blocks = sh.blocks > 0 ? sh.blocks : device_cu_count() * (per_cu < 1 ? 1 : per_cu);
   auto kern = k_fused256<PREC, MS>;
   hipLaunchKernelGGL(kern, dim3(blocks), dim3(sh.waves * 64), lds, (hipStream_t)stream, b.words,
                      b.symlen, b.n_streams, c.E, S, c.lmax, c.n_books, c.n_rows, sh.wpc, c.lut, c.deq_val,
-                     c.deq_zone, c.row_of_bin, c.basis, p.hdr, p.chunk_meta, gamma, out, status);
+                     c.deq_zone, c.row_of_bin, p.basis_split, p.hdr, p.chunk_meta, gamma, out, status);
   return (int)hipGetLastError();
 }
 
@@ -382,6 +420,8 @@ bool mfma256_supported(int E, int precision) {
   if (precision < FPTC_FP16 || precision > FPTC_BF16X3) return false;
   return E >= 1 && E <= N256;
 }
+
+size_t basis_split256_bytes(int N) { return N == N256 ? (size_t)kMaxBlocks256 * block_basis_bytes(3) : 0; }
 
 bool fused256_supported(const fptc_codec &c, int precision, int wpc, int waves) {
   if (!mfma256_supported(c.E, precision) || waves < 1 || waves > kMaxWaves256) return false;
