@@ -44,7 +44,7 @@ __host__ __device__ constexpr size_t table_bytes(int bpieces, int n_books, int n
 // tile per wave.
 __host__ __device__ constexpr size_t mfma_lds_bytes(int bpieces, int N, int Kp, int n_books, int n_rows, int E) {
   return (size_t)bpieces * N * (Kp + 8) * 2 + table_bytes(bpieces, n_books, n_rows, E) +
-         (size_t)kWaves * a16((size_t)kTileWindows * E + 16);
+         (size_t)kWaves * (16 + a16((size_t)kTileWindows * E + 16));
 }
 
 // The symbols of a 32-window tile, 16 bytes per lane per round: R rounds of
@@ -138,7 +138,7 @@ __global__ void __launch_bounds__(kThreads, NT >= 4 ? 2 : (NT == 2 ? 3 : 4)) k_d
 
   const int lane = threadIdx.x & 63, col = lane & 31, h = lane >> 5;
   const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  unsigned char *sb = bufs + (size_t)wid * a16((size_t)kTileWindows * E + 16);
+  unsigned char *sb = bufs + (size_t)wid * (16 + a16((size_t)kTileWindows * E + 16)) + 16;
   const int64_t n_chunks = hdr[0];
   const int64_t cstride = (int64_t)gridDim.x * kWaves;
   const float oscale = 1.0f / bscale;
@@ -189,8 +189,12 @@ __global__ void __launch_bounds__(kThreads, NT >= 4 ? 2 : (NT == 2 ? 3 : 4)) k_d
       if (tt == 0) settle_tile_syms(nx);  // before this chunk's stores
       float *win0 = out + cm.out_base + (int64_t)tt * kTileWindows * N;
       const int rem = cm.out_len - tt * kTileWindows * N;
+      if (E == N) {  // stage through the consumed symbol tile
+        store_tile_staged<NT>(win0, acc, reinterpret_cast<float *>(sb) - 4, h, col, lane, rem, oscale);
+      } else {
 #pragma unroll
-      for (int t = 0; t < NT; ++t) store_rows(win0, N, acc[t], t, h, col, rem, oscale);
+        for (int t = 0; t < NT; ++t) store_rows(win0, N, acc[t], t, h, col, rem, oscale);
+      }
       wave_sync_lds();
     }
     settle_tile_syms(nx);

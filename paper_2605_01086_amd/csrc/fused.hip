@@ -164,8 +164,12 @@ __global__ void __launch_bounds__(64 * max_fused_waves(NT * 32)) k_fused(const u
         // the chunk's windows are consecutive in one stream
         float *win0 = out + cm.out_base + (int64_t)tt * kTileWindows * N;
         const int rem = cm.out_len - tt * kTileWindows * N;
+        if (E == N && wpc >= kTileWindows) {  // a quarter tile fits in the consumed symbol buffer
+          store_tile_staged<NT>(win0, acc, reinterpret_cast<float *>(sb) - 4, h, col, lane, rem, oscale);
+        } else {
 #pragma unroll
-        for (int t = 0; t < NT; ++t) store_rows(win0, N, acc[t], t, h, col, rem, oscale);
+          for (int t = 0; t < NT; ++t) store_rows(win0, N, acc[t], t, h, col, rem, oscale);
+        }
       }
       wave_sync_lds();
     }

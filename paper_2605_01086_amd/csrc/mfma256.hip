@@ -335,8 +335,12 @@ __global__ void __launch_bounds__(kMaxWaves256 * 64) k_fused256(const uint64_t *
       }
       float *win0 = out + cm.out_base + (int64_t)tt * kTileWindows * N256;
       const int rem = tile_active ? cm.out_len - tt * kTileWindows * N256 : 0;
+      if (E == N256 && wpc >= kTileWindows && tile_active) {  // stage through the consumed symbol buffer
+        store_tile_staged<NT256>(win0, acc, reinterpret_cast<float *>(sb) - 4, h, col, lane, rem, oscale);
+      } else {
 #pragma unroll
-      for (int t = 0; t < NT256; ++t) store_rows(win0, N256, acc[t], t, h, col, rem, oscale);
+        for (int t = 0; t < NT256; ++t) store_rows(win0, N256, acc[t], t, h, col, rem, oscale);
+      }
     }
     wave_sync_lds();
     cm = nm;

@@ -276,6 +276,59 @@ __device__ inline void tile_contract(f16v (&acc)[NT], const unsigned char *sb, i
   }
 }
 
+typedef float f4u __attribute__((ext_vector_type(4), aligned(4)));  // 16 bytes, 4-byte aligned
+
+// Order a wavefront's LDS writes before its later LDS reads by other lanes.
+__device__ inline void wave_sync_lds() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+typedef float f4a __attribute__((ext_vector_type(4)));  // 16 bytes, 16-byte aligned
+
+// Store a whole 32-window tile through LDS so that global memory sees
+// contiguous, 16-byte aligned 16-byte stores.  The tile's windows are
+// consecutive in one stream: win0 is the first sample of window 0 and rem
+// the samples from there to the end of the tile's data.  Eight windows (a
+// quarter, 8 N floats) at a time are scattered into `stage` in output order,
+// shifted by the output's misalignment (0..3 floats), then read back as
+// aligned 16-byte vectors, each lane writing whole 16-byte blocks (partial
+// blocks at the quarter's ends element by element).  stage must be 16-byte
+// aligned with 8 N + 4 floats of room (the caller passes its consumed symbol
+// buffer, starting 16 bytes into the prefix before it).
+template <int NT>
+__device__ inline void store_tile_staged(float *win0, const f16v (&acc)[NT], float *stage, int h, int col, int lane,
+                                         int rem, float scale) {
+  constexpr int N = NT * 32, QF = 8 * N;
+  const int delta = (int)((reinterpret_cast<uintptr_t>(win0) >> 2) & 3);
+#pragma unroll 1
+  for (int q = 0; q < 4; ++q) {
+    const int qrem = rem - q * QF;  // wave-uniform
+    if (qrem <= 0) break;
+    const int qn = qrem < QF ? qrem : QF;
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) stage[delta + (4 * h + j) * N + 32 * t + col] = acc[t][4 * q + j] * scale;
+    wave_sync_lds();
+    float *g = win0 + q * QF - delta;  // 16-byte aligned
+    const int nvec = (qn + delta + 3) >> 2;
+    for (int m = lane; m < nvec; m += 64) {
+      const f4a v = *reinterpret_cast<const f4a *>(stage + 4 * m);
+      const int i0 = 4 * m - delta;  // quarter-relative index of v.x
+      if (i0 >= 0 && i0 + 4 <= qn) {
+        *reinterpret_cast<f4a *>(g + 4 * m) = v;
+      } else {
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          if (i0 + i >= 0 && i0 + i < qn) g[4 * m + i] = v[i];
+      }
+    }
+    wave_sync_lds();
+  }
+}
+
 // Store output tile t (samples 32 t .. 32 t + 31 of every window) of a block
 // of up to 32 consecutive windows of one stream: win0 = first sample of the
 // block's window 0, rem = samples from there to the end of the block (window
@@ -293,12 +346,6 @@ __device__ inline void store_rows(float *win0, int N, const f16v &acc, int t, in
   }
 }
 
-// Order a wavefront's LDS writes before its later LDS reads by other lanes.
-__device__ inline void wave_sync_lds() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
 
 // Inclusive prefix sum across a 64-lane wavefront with DPP row shifts and row
 // broadcasts (no LDS round trips).
