@@ -21,8 +21,10 @@
 namespace fptc {
 namespace {
 
+// prefix | up to 15 bytes of destination misalignment | the chunk's symbols |
+// room for the two bytes a decode lookup may write past the last run
 __host__ __device__ inline size_t decode_wave_bytes(int wpc, int E) {
-  return (size_t)kSymPrefix + ((((size_t)wpc * E + 16) + 15) & ~(size_t)15);
+  return (size_t)kSymPrefix + ((((size_t)wpc * E + 32) + 15) & ~(size_t)15);
 }
 
 // LDS: lookup tables, then one symbol buffer per wave; the multi-symbol

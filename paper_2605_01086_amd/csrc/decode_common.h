@@ -14,7 +14,10 @@
 //    With a mean code length of a few bits this cuts the serial lookups per
 //    word by 2-3x.  A per-codebook code-length table (symbol -> length) lets
 //    the last lookup of a run discount symbols that lie past the run, so the
-//    consumed-bit count stays exact for the overrun check.
+//    consumed-bit count stays exact for the overrun check.  Each lookup
+//    writes all three symbol bytes; the at most two that fall past a lane's
+//    run land on the first two positions of a later run, and every run writes
+//    its first two symbols again once all lanes have finished.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -136,26 +139,36 @@ __device__ inline int decode_word(uint64_t wd, unsigned char *p, int cnt, const 
   int bits = 0, err = 0;
   if constexpr (MS) {
     const uint32_t *L = reinterpret_cast<const uint32_t *>(lut);
+    const uint64_t w0 = wd;
+    unsigned char *const p0 = p;
     uint32_t e, fl = 0;
-    int rem;
     do {
       e = L[(uint32_t)(wd >> 32) >> hs];
       const int len = (e >> 24) & 15;
       wd <<= len;
       bits += len;
       fl |= e;
-      rem = (int)(pe - p);
+      // all three bytes, whatever the count: up to two may land past this
+      // run, on the start of a later run, which writes its first two symbols
+      // again after every lane's loop (below)
       p[0] = (unsigned char)e;
-      if (rem > 1) p[1] = (unsigned char)(e >> 8);
-      if (rem > 2) p[2] = (unsigned char)(e >> 16);
+      p[1] = (unsigned char)(e >> 8);
+      p[2] = (unsigned char)(e >> 16);
       p += (e >> 28) & 3;
     } while (p < pe);
     // symbols of the last lookup past the run are not part of this word's count
     const int c = (e >> 28) & 3;
+    const int rem = (int)(pe - p) + c;  // symbols the last lookup still had to give
     const int l1 = cl[(e >> 8) & 255u], l2 = cl[(e >> 16) & 255u];
     bits -= (c > 1 && rem < 2) ? l1 : 0;
     bits -= (c > 2 && rem < 3) ? l2 : 0;
     if (fl & kLutMissing) err |= FPTC_STREAM_OVERRUN;
+    // the first two symbols of this run, written again now that every lane of
+    // the wave has left its loop
+    const uint32_t f0 = L[(uint32_t)(w0 >> 32) >> hs];
+    const uint32_t f1 = L[(uint32_t)((w0 << ((f0 >> 24) & 15)) >> 32) >> hs];
+    p0[0] = (unsigned char)f0;
+    if (cnt > 1) p0[1] = (unsigned char)(((f0 >> 28) & 3) > 1 ? (f0 >> 8) : f1);
   } else {
     const uint16_t *L = reinterpret_cast<const uint16_t *>(lut);
     do {

@@ -4,6 +4,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "fptc_internal.h"
 
 namespace fptc {
@@ -127,12 +129,12 @@ __device__ inline void stage_pieces(uint32_t *pq, const float *deq_val, int n, i
 
 // Coefficient pieces of one k-step without per-stream scales: the 8 symbols
 // (s0, s1: byte j is bin k0 + j) looked up in the pre-split table of their
-// rows (pq: the book's table; rb: row of each bin when multi_row) and
+// rows (pq: the book's table; rb: row of each bin when MULTI_ROW) and
 // repacked pairwise with byte permutes.  Returns whether any low piece is
 // nonzero.  Bins must lie inside [0, E) (E a multiple of 16).
-template <int PREC>
-__device__ inline bool gather8(uint32_t s0, uint32_t s1, int k0, const uint32_t *pq, bool multi_row,
-                               const uint8_t *rb, u8v (&a)[Traits<PREC>::kAPieces]) {
+template <int PREC, bool MULTI_ROW>
+__device__ inline bool gather8(uint32_t s0, uint32_t s1, int k0, const uint32_t *pq, const uint8_t *rb,
+                               u8v (&a)[Traits<PREC>::kAPieces]) {
   using T = Traits<PREC>;
   constexpr int AP = T::kAPieces;
   static_assert(AP <= 2, "pre-split table holds at most two pieces");
@@ -140,7 +142,7 @@ __device__ inline bool gather8(uint32_t s0, uint32_t s1, int k0, const uint32_t 
 #pragma unroll
   for (int j = 0; j < 8; ++j) {
     const uint32_t sym = ((j < 4 ? s0 : s1) >> (8 * (j & 3))) & 255u;
-    const uint32_t row = multi_row ? (uint32_t)rb[k0 + j] : 0u;
+    const uint32_t row = MULTI_ROW ? (uint32_t)rb[k0 + j] : 0u;
     t[j] = pq[row * 256 + sym];
   }
   uint32_t hi[4], lo[4];
@@ -209,11 +211,12 @@ __device__ inline void stage_basis(uint16_t *Bs, const float *basis, int N, int 
   }
 }
 
-// One 32-window tile of a wavefront: acc[t] (output rows t*32 ..) of this
-// lane's window from the window's symbols at sb[base + bin] in LDS.  k-steps
-// run from the highest bins down.  Without scales, with E a multiple of 16 and
-// at most two pieces, coefficients come from the pre-split table pq (two
-// k-steps in flight); otherwise through dequant8.  Lanes whose window is not
+// One 32-window tile of a wavefront: acc[t] (output samples t*32 ..) of the
+// tile's windows from their symbols at sb[base + bin] in LDS.  k-steps run
+// from the highest bins down.  Without scales, with E a multiple of 16 and at
+// most two pieces, coefficients come from the pre-split table pq (the row
+// lookup compiled out when the book has one row); otherwise through
+// dequant8.  Lanes whose window is not
 // valid compute on the clamped window's symbols; only their lower-piece flag is
 // masked, so valid columns get exactly the general path's arithmetic.
 //   Bs: split basis [piece][n][RS]; rb/tv/tz/pq: this book's tables.
@@ -233,24 +236,22 @@ __device__ inline void tile_contract(f16v (&acc)[NT], const unsigned char *sb, i
     for (int r = 0; r < 16; ++r) acc[t][r] = 0.0f;
   if constexpr (AP <= 2) {
     if (!gamma && e_vec) {
-      const bool multi_row = n_rows > 1;
-      auto step = [&](int ss) {
-        const int k0 = h * KH + 8 * ss;
-        const uint2 u = *reinterpret_cast<const uint2 *>(sb + base + k0);
-        u8v a[AP];
-        const bool r = gather8<PREC>(u.x, u.y, k0, pq, multi_row, rb, a);
-        const bool any_rest = AP > 1 && __any(r && valid);
-        mfma_step<PREC, NT>(acc, a, Bs + col * RS + k0, 32 * RS, N * RS, any_rest);
-      };
-      // pairs of k-steps in one block so that the second step's reads
-      // overlap the first step's matrix ops; same order as one at a time
-      int ss = S - 1;
-      if (S & 1) step(ss--);
+      auto run = [&](auto multi_row) {
+        constexpr bool MR = decltype(multi_row)::value;
 #pragma unroll 1
-      for (; ss >= 1; ss -= 2) {
-        step(ss);
-        step(ss - 1);
-      }
+        for (int ss = S - 1; ss >= 0; --ss) {
+          const int k0 = h * KH + 8 * ss;
+          const uint2 u = *reinterpret_cast<const uint2 *>(sb + base + k0);
+          u8v a[AP];
+          const bool r = gather8<PREC, MR>(u.x, u.y, k0, pq, rb, a);
+          const bool any_rest = AP > 1 && __any(r && valid);
+          mfma_step<PREC, NT>(acc, a, Bs + col * RS + k0, 32 * RS, N * RS, any_rest);
+        }
+      };
+      if (n_rows > 1)
+        run(std::true_type{});
+      else
+        run(std::false_type{});
       return;
     }
   }
