@@ -294,8 +294,9 @@ typedef float f4a __attribute__((ext_vector_type(4)));  // 16 bytes, 16-byte ali
 // the samples from there to the end of the tile's data.  Eight windows (a
 // quarter, 8 N floats) at a time are scattered into `stage` in output order,
 // shifted by the output's misalignment (0..3 floats), then read back as
-// aligned 16-byte vectors, each lane writing whole 16-byte blocks (partial
-// blocks at the quarter's ends element by element).  stage must be 16-byte
+// aligned 16-byte vectors, each lane writing whole 16-byte blocks (the
+// floats of partial blocks at the quarter's ends spread over lanes 0..7 and
+// written by one store instruction).  stage must be 16-byte
 // aligned with 8 N + 4 floats of room (the caller passes its consumed symbol
 // buffer, starting 16 bytes into the prefix before it).
 template <int NT>
@@ -315,16 +316,18 @@ __device__ inline void store_tile_staged(float *win0, const f16v (&acc)[NT], flo
     wave_sync_lds();
     float *g = win0 + q * QF - delta;  // 16-byte aligned
     const int nvec = (qn + delta + 3) >> 2;
+    // whole 16-byte blocks: every vector but possibly the first and the last
     for (int m = lane; m < nvec; m += 64) {
-      const f4a v = *reinterpret_cast<const f4a *>(stage + 4 * m);
-      const int i0 = 4 * m - delta;  // quarter-relative index of v.x
-      if (i0 >= 0 && i0 + 4 <= qn) {
-        *reinterpret_cast<f4a *>(g + 4 * m) = v;
-      } else {
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-          if (i0 + i >= 0 && i0 + i < qn) g[4 * m + i] = v[i];
-      }
+      const int i0 = 4 * m - delta;  // quarter-relative index of the block's first float
+      if (i0 >= 0 && i0 + 4 <= qn) *reinterpret_cast<f4a *>(g + 4 * m) = *reinterpret_cast<const f4a *>(stage + 4 * m);
+    }
+    // the floats of a partial first or last block, one per lane (lanes 0..7),
+    // so that they leave as a single store instruction
+    if (lane < 8) {
+      const int m = lane < 4 ? 0 : nvec - 1;
+      const int i0 = 4 * m - delta, e = i0 + (lane & 3);
+      const bool whole = i0 >= 0 && i0 + 4 <= qn;
+      if (!whole && (lane < 4 || nvec > 1) && e >= 0 && e < qn) g[4 * m + (lane & 3)] = stage[4 * m + (lane & 3)];
     }
     wave_sync_lds();
   }
