@@ -222,10 +222,11 @@ def cpu_baseline(words, symlen, word_off, sample_off, dom, lens_tab, q, budget_s
 
 # Sources of the kernel each roofline stage names; an HBM-traffic summary in
 # profiles/ applies only while these hash to the digest recorded in it.
+PLAN_KERNELS = "k_plan_streams+k_plan_seg_sums+k_plan_stream_scan+k_plan_seg_chunks"
 KERNEL_SOURCES = {
-    "fused": ["fused.hip", "decode_common.h", "mfma_common.h", "fptc_internal.h"],
+    "fused": ["fused.hip", "mfma256.hip", "decode_common.h", "mfma_common.h", "fptc_internal.h"],
     "decode": ["decode.hip", "decode_common.h", "mfma_common.h", "fptc_internal.h"],
-    "dequant_idct": ["dqidct_mfma.hip", "dqidct.hip", "mfma_common.h", "fptc_internal.h"],
+    "dequant_idct": ["dqidct_mfma.hip", "dqidct.hip", "mfma256.hip", "mfma_common.h", "fptc_internal.h"],
     "plan": ["plan.hip", "fptc_internal.h"],
 }
 
@@ -358,14 +359,15 @@ def main():
         names = ["plan", "fused"]
         stage_ms = per_kernel[:2]
         alg = {"plan": batch.n_words + batch.header_bytes, "fused": comp_bytes + out_bytes}
-        kern = {"plan": "k_plan_chunks", "fused": f"k_fused<{args.precision}>"}
+        kern = {"plan": PLAN_KERNELS, "fused": f"k_fused{'256' if q.N == 256 else ''}<{args.precision}>"}
     else:
         names = ["plan", "decode", "dequant_idct"]
         stage_ms = per_kernel
         alg = {"plan": batch.n_words + batch.header_bytes, "decode": comp_bytes + batch.n_symbols,
                "dequant_idct": batch.n_symbols + out_bytes}
-        kern = {"plan": "k_plan_chunks", "decode": "k_decode",
-                "dequant_idct": "k_dqidct_f32" if args.precision == "fp32" else f"k_dqidct_mfma<{args.precision}>"}
+        kern = {"plan": PLAN_KERNELS, "decode": "k_decode",
+                "dequant_idct": "k_dqidct_f32" if args.precision == "fp32"
+                else f"k_dqidct_mfma{'256' if q.N == 256 else ''}<{args.precision}>"}
     dom_k = int(np.argmax(stage_ms))
     kname = names[dom_k]
     achieved = alg[kname] / (stage_ms[dom_k] * 1e-3) / 1e9
