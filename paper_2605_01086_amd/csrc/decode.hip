@@ -58,25 +58,20 @@ __global__ void __launch_bounds__(1024) k_decode(const uint64_t *__restrict__ wo
   const int hs = 32 - lmax;
 
   // Software pipeline over this wave's chunks: the words of the next chunk
-  // are requested before this chunk decodes (their meta one chunk earlier)
-  // and waited for right after the decode, before this chunk's stores; with
-  // in-order vector memory counters that wait also covers the previous
-  // chunk's stores, which had the decode to drain.
+  // (and the record of the one after) are requested before this chunk
+  // decodes and waited for right after the decode, before this chunk's
+  // stores; with in-order vector memory counters that wait also covers the
+  // previous chunk's stores, which had the decode to drain.
   int64_t c = (int64_t)blockIdx.x * waves_per_block + wid;
-  ChunkMeta cm{}, nm{};
-  cm.first_word = nm.first_word = -1;
+  ChunkMeta cm = meta_from_lanes(load_meta_lane(meta, c, n_chunks, lane), c < n_chunks);
+  const uint32_t vn = load_meta_lane(meta, c + cstride, n_chunks, lane);
   ChunkWords cw{};
-  if (c < n_chunks) {
-    cm = meta[c];
-    load_chunk_words(words, symlen, cm.first_word, cm.word_end, lane, cw);
-  }
-  if (c + cstride < n_chunks) nm = meta[c + cstride];
+  if (c < n_chunks) load_chunk_words(words, symlen, cm.first_word, cm.word_end, lane, cw);
+  ChunkMeta nm = meta_from_lanes(vn, c + cstride < n_chunks);
   for (; c < n_chunks; c += cstride) {
+    const uint32_t vm = load_meta_lane(meta, c + 2 * cstride, n_chunks, lane);
     ChunkWords nx{};
     if (c + cstride < n_chunks) load_chunk_words(words, symlen, nm.first_word, nm.word_end, lane, nx);
-    ChunkMeta mm{};
-    mm.first_word = -1;
-    if (c + 2 * cstride < n_chunks) mm = meta[c + 2 * cstride];
     const bool ok = cm.first_word >= 0;  // else the stream's symbol count is wrong; already flagged
     const int s = cm.stream < 0 ? 0 : (cm.stream >= n_streams ? n_streams - 1 : cm.stream);
     const int book = cm.book < n_books && cm.book >= 0 ? cm.book : 0;
@@ -91,6 +86,8 @@ __global__ void __launch_bounds__(1024) k_decode(const uint64_t *__restrict__ wo
                              cl + book * 256, hs, buf + mis, lane);
     }
     settle_chunk_words(nx);
+    settle_lane(vm);
+    const ChunkMeta mm = meta_from_lanes(vm, c + 2 * cstride < n_chunks);
     cw = nx;
     if (ok) {
       if (err && status) atomicOr(&status[s], err);

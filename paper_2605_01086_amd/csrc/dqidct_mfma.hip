@@ -145,30 +145,27 @@ __global__ void __launch_bounds__(kThreads, NT >= 4 ? 2 : (NT == 2 ? 3 : 4)) k_d
   const bool vec16 = (E % 16) == 0 && (reinterpret_cast<uintptr_t>(symbols) & 15) == 0;
 
   int64_t c = (int64_t)blockIdx.x * kWaves + wid;
-  ChunkMeta cm{}, nm{};
-  cm.n_windows = nm.n_windows = 0;
+  ChunkMeta cm = meta_from_lanes(load_meta_lane(meta, c, n_chunks, lane), c < n_chunks);
+  const uint32_t vn = load_meta_lane(meta, c + cstride, n_chunks, lane);
   TileSyms<NT> cur{};
-  if (c < n_chunks) {
-    cm = meta[c];
+  if (c < n_chunks)
     load_tile_syms(symbols, b.n_symbols, cm.sym_base, min(kTileWindows, cm.n_windows) * E, vec16, lane, cur);
-  }
-  if (c + cstride < n_chunks) nm = meta[c + cstride];
+  ChunkMeta nm = meta_from_lanes(vn, c + cstride < n_chunks);
+  auto stream_of = [&](const ChunkMeta &m) {
+    return m.stream < 0 ? 0 : (m.stream >= b.n_streams ? b.n_streams - 1 : m.stream);
+  };
+  // per-stream scales of the current chunk, requested one chunk ahead
+  float vg = load_gamma_lane(gamma, stream_of(cm), lane);
+  settle_lane(vg);
   for (; c < n_chunks; c += cstride) {
+    const int book = cm.book < n_books && cm.book >= 0 ? cm.book : 0;
+    const int w_cnt = cm.n_windows;
+    const float g0 = lane_float(vg, 0), g1 = lane_float(vg, 1), g2 = lane_float(vg, 2);
+    const uint32_t vm = load_meta_lane(meta, c + 2 * cstride, n_chunks, lane);
+    const float vgn = load_gamma_lane(gamma, stream_of(nm), lane);
     TileSyms<NT> nx{};
     if (c + cstride < n_chunks)
       load_tile_syms(symbols, b.n_symbols, nm.sym_base, min(kTileWindows, nm.n_windows) * E, vec16, lane, nx);
-    ChunkMeta mm{};
-    mm.n_windows = 0;
-    if (c + 2 * cstride < n_chunks) mm = meta[c + 2 * cstride];
-    const int s = cm.stream < 0 ? 0 : (cm.stream >= b.n_streams ? b.n_streams - 1 : cm.stream);
-    const int book = cm.book < n_books && cm.book >= 0 ? cm.book : 0;
-    const int w_cnt = cm.n_windows;
-    float g0 = 1.0f, g1 = 1.0f, g2 = 1.0f;
-    if (gamma) {
-      g0 = gamma[3 * (int64_t)s];
-      g1 = gamma[3 * (int64_t)s + 1];
-      g2 = gamma[3 * (int64_t)s + 2];
-    }
     for (int tt = 0; tt * kTileWindows < w_cnt; ++tt) {
       const int wt = min(kTileWindows, w_cnt - tt * kTileWindows);
       if (tt == 0) {
@@ -186,11 +183,18 @@ __global__ void __launch_bounds__(kThreads, NT >= 4 ? 2 : (NT == 2 ? 3 : 4)) k_d
       tile_contract<PREC, NT>(acc, sb, base, h, col, S, E, valid > 0, Bs, RS, Rb + book * E,
                               Tv + book * n_rows * 256, Tz + book * n_rows * 256, Pq + book * n_rows * 256, n_rows,
                               gamma, g0, g1, g2);
-      if (tt == 0) settle_tile_syms(nx);  // before this chunk's stores
+      if (tt == 0) {  // before this chunk's stores
+        settle_tile_syms(nx);
+        settle_lane(vm);
+        settle_lane(vgn);
+      }
       float *win0 = out + cm.out_base + (int64_t)tt * kTileWindows * N;
       const int rem = cm.out_len - tt * kTileWindows * N;
       if (E == N) {  // stage through the consumed symbol tile
-        store_tile_staged<NT>(win0, acc, reinterpret_cast<float *>(sb) - 4, h, col, lane, rem, oscale);
+        if (rem >= kTileWindows * N)
+          store_tile_whole<NT>(win0, acc, reinterpret_cast<float *>(sb) - 4, h, col, lane, oscale);
+        else
+          store_tile_staged<NT>(win0, acc, reinterpret_cast<float *>(sb) - 4, h, col, lane, rem, oscale);
       } else {
 #pragma unroll
         for (int t = 0; t < NT; ++t) store_rows(win0, N, acc[t], t, h, col, rem, oscale);
@@ -198,9 +202,12 @@ __global__ void __launch_bounds__(kThreads, NT >= 4 ? 2 : (NT == 2 ? 3 : 4)) k_d
       wave_sync_lds();
     }
     settle_tile_syms(nx);
+    settle_lane(vm);
+    settle_lane(vgn);
     cur = nx;
     cm = nm;
-    nm = mm;
+    nm = meta_from_lanes(vm, c + 2 * cstride < n_chunks);
+    vg = vgn;
   }
 }
 

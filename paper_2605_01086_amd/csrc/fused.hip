@@ -107,29 +107,25 @@ __global__ void __launch_bounds__(64 * max_fused_waves(NT * 32)) k_fused(const u
   const int64_t cstride = (int64_t)gridDim.x * waves;
 
   // Software pipeline over this wave's chunks c, c + cstride, ...: the words
-  // of chunk i+1 are requested before chunk i decodes (their meta one chunk
-  // earlier still) and are waited for right after that decode, before chunk
-  // i's stores.  Vector memory counters retire in order, so this one wait
-  // also covers chunk i-1's stores, which had the whole decode to drain.
+  // of chunk i+1 (and the record of chunk i+2) are requested before chunk i
+  // decodes and are waited for right after that decode, before chunk i's
+  // stores.  Vector memory counters retire in order, so this one wait also
+  // covers chunk i-1's stores, which had the whole decode to drain.
   int64_t c = (int64_t)blockIdx.x * waves + wid;
-  ChunkMeta cm{}, nm{};
-  cm.first_word = nm.first_word = -1;
+  ChunkMeta cm = meta_from_lanes(load_meta_lane(meta, c, n_chunks, lane), c < n_chunks);
+  const uint32_t vn = load_meta_lane(meta, c + cstride, n_chunks, lane);
   ChunkWords cw{};
-  if (c < n_chunks) {
-    cm = meta[c];
-    load_chunk_words(words, symlen, cm.first_word, cm.word_end, lane, cw);
-  }
-  if (c + cstride < n_chunks) nm = meta[c + cstride];
+  if (c < n_chunks) load_chunk_words(words, symlen, cm.first_word, cm.word_end, lane, cw);
+  ChunkMeta nm = meta_from_lanes(vn, c + cstride < n_chunks);
   for (; c < n_chunks; c += cstride) {
-    ChunkWords nx{};
-    if (c + cstride < n_chunks) load_chunk_words(words, symlen, nm.first_word, nm.word_end, lane, nx);
-    ChunkMeta mm{};
-    mm.first_word = -1;
-    if (c + 2 * cstride < n_chunks) mm = meta[c + 2 * cstride];
     const bool ok = cm.first_word >= 0;  // else the stream's symbol count is wrong; already flagged
     const int s = cm.stream < 0 ? 0 : (cm.stream >= n_streams ? n_streams - 1 : cm.stream);
     const int book = cm.book < n_books && cm.book >= 0 ? cm.book : 0;
     const int w_cnt = cm.n_windows;
+    const float vg = load_gamma_lane(gamma, s, lane);
+    const uint32_t vm = load_meta_lane(meta, c + 2 * cstride, n_chunks, lane);
+    ChunkWords nx{};
+    if (c + cstride < n_chunks) load_chunk_words(words, symlen, nm.first_word, nm.word_end, lane, nx);
 
     // ---- 1. decode the chunk's symbols into sb[0 .. w_cnt * E)
     int err = 0;
@@ -140,15 +136,13 @@ __global__ void __launch_bounds__(64 * max_fused_waves(NT * 32)) k_fused(const u
                              cl + book * 256, hs, sb, lane);
     }
     settle_chunk_words(nx);
+    settle_lane(vm);
+    settle_lane(vg);
+    const ChunkMeta mm = meta_from_lanes(vm, c + 2 * cstride < n_chunks);
     cw = nx;
     if (ok) {
       if (err && status) atomicOr(&status[s], err);
-      float g0 = 1.0f, g1 = 1.0f, g2 = 1.0f;
-      if (gamma) {
-        g0 = gamma[3 * (int64_t)s];
-        g1 = gamma[3 * (int64_t)s + 1];
-        g2 = gamma[3 * (int64_t)s + 2];
-      }
+      const float g0 = lane_float(vg, 0), g1 = lane_float(vg, 1), g2 = lane_float(vg, 2);
       wave_sync_lds();
 
       // ---- 2. per 32 windows: dequantize, contract, store
@@ -165,7 +159,10 @@ __global__ void __launch_bounds__(64 * max_fused_waves(NT * 32)) k_fused(const u
         float *win0 = out + cm.out_base + (int64_t)tt * kTileWindows * N;
         const int rem = cm.out_len - tt * kTileWindows * N;
         if (E == N && wpc >= kTileWindows) {  // a quarter tile fits in the consumed symbol buffer
-          store_tile_staged<NT>(win0, acc, reinterpret_cast<float *>(sb) - 4, h, col, lane, rem, oscale);
+          if (rem >= kTileWindows * N)
+            store_tile_whole<NT>(win0, acc, reinterpret_cast<float *>(sb) - 4, h, col, lane, oscale);
+          else
+            store_tile_staged<NT>(win0, acc, reinterpret_cast<float *>(sb) - 4, h, col, lane, rem, oscale);
         } else {
 #pragma unroll
           for (int t = 0; t < NT; ++t) store_rows(win0, N, acc[t], t, h, col, rem, oscale);

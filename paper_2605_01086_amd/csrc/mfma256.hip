@@ -265,30 +265,25 @@ __global__ void __launch_bounds__(kMaxWaves256 * 64) k_fused256(const uint64_t *
   // Software pipeline over this wave's chunks (see the resident fused
   // kernel): next chunk's words requested before this chunk decodes, waited
   // for right after the decode, before this chunk's stores.
-  ChunkMeta cm{}, nm{};
-  cm.first_word = nm.first_word = -1;
-  cm.n_windows = 0;
+  ChunkMeta cm, nm;
   ChunkWords cw{};
   {
     const int64_t c = (int64_t)blockIdx.x * waves + wid;
-    if (c < n_chunks) {
-      cm = meta[c];
-      load_chunk_words(words, symlen, cm.first_word, cm.word_end, lane, cw);
-    }
-    if (c + cstride < n_chunks) nm = meta[c + cstride];
+    cm = meta_from_lanes(load_meta_lane(meta, c, n_chunks, lane), c < n_chunks);
+    const uint32_t vn = load_meta_lane(meta, c + cstride, n_chunks, lane);
+    if (c < n_chunks) load_chunk_words(words, symlen, cm.first_word, cm.word_end, lane, cw);
+    nm = meta_from_lanes(vn, c + cstride < n_chunks);
   }
   for (int64_t c0 = (int64_t)blockIdx.x * waves; c0 < n_chunks; c0 += cstride) {
     const int64_t c = c0 + wid;
-    ChunkWords nx{};
-    if (c + cstride < n_chunks) load_chunk_words(words, symlen, nm.first_word, nm.word_end, lane, nx);
-    ChunkMeta mm{};
-    mm.first_word = -1;
-    mm.n_windows = 0;
-    if (c + 2 * cstride < n_chunks) mm = meta[c + 2 * cstride];
     const bool active = c < n_chunks && cm.first_word >= 0;
     const int s = cm.stream < 0 ? 0 : (cm.stream >= n_streams ? n_streams - 1 : cm.stream);
     const int book = cm.book < n_books && cm.book >= 0 ? cm.book : 0;
     const int w_cnt = active ? cm.n_windows : 0;
+    const float vg = load_gamma_lane(active ? gamma : nullptr, s, lane);
+    const uint32_t vm = load_meta_lane(meta, c + 2 * cstride, n_chunks, lane);
+    ChunkWords nx{};
+    if (c + cstride < n_chunks) load_chunk_words(words, symlen, nm.first_word, nm.word_end, lane, nx);
     int err = 0;
     if (active) {
       const void *lb = MS ? (const void *)(reinterpret_cast<const uint32_t *>(lds) + (book << lmax))
@@ -297,14 +292,12 @@ __global__ void __launch_bounds__(kMaxWaves256 * 64) k_fused256(const uint64_t *
                              cl + book * 256, hs, sb, lane);
     }
     settle_chunk_words(nx);
+    settle_lane(vm);
+    settle_lane(vg);
+    const ChunkMeta mm = meta_from_lanes(vm, c + 2 * cstride < n_chunks);
     cw = nx;
     if (err && status) atomicOr(&status[s], err);
-    float g0 = 1.0f, g1 = 1.0f, g2 = 1.0f;
-    if (active && gamma) {
-      g0 = gamma[3 * (int64_t)s];
-      g1 = gamma[3 * (int64_t)s + 1];
-      g2 = gamma[3 * (int64_t)s + 2];
-    }
+    const float g0 = lane_float(vg, 0), g1 = lane_float(vg, 1), g2 = lane_float(vg, 2);
     wave_sync_lds();
     for (int tt = 0; tt < ntile_max; ++tt) {
       const int wr = tt * kTileWindows + col;
@@ -336,7 +329,10 @@ __global__ void __launch_bounds__(kMaxWaves256 * 64) k_fused256(const uint64_t *
       float *win0 = out + cm.out_base + (int64_t)tt * kTileWindows * N256;
       const int rem = tile_active ? cm.out_len - tt * kTileWindows * N256 : 0;
       if (E == N256 && wpc >= kTileWindows && tile_active) {  // stage through the consumed symbol buffer
-        store_tile_staged<NT256>(win0, acc, reinterpret_cast<float *>(sb) - 4, h, col, lane, rem, oscale);
+        if (rem >= kTileWindows * N256)
+          store_tile_whole<NT256>(win0, acc, reinterpret_cast<float *>(sb) - 4, h, col, lane, oscale);
+        else
+          store_tile_staged<NT256>(win0, acc, reinterpret_cast<float *>(sb) - 4, h, col, lane, rem, oscale);
       } else {
 #pragma unroll
         for (int t = 0; t < NT256; ++t) store_rows(win0, N256, acc[t], t, h, col, rem, oscale);

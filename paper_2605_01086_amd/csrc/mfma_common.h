@@ -333,6 +333,47 @@ __device__ inline void store_tile_staged(float *win0, const f16v (&acc)[NT], flo
   }
 }
 
+// Store a whole 32-window tile (rem >= 32 N) through LDS.  The quarters are
+// cut on the output's 16-byte grid instead of at window boundaries: quarter q
+// stages tile floats [q QF - delta, (q + 1) QF - delta), which takes in the
+// last delta floats of quarter q - 1's windows.  Every block inside the tile
+// is then whole and leaves with one 16-byte store; only the tile's first and
+// last blocks are partial, and their floats (at most 3 + 3) leave together,
+// one per lane, after the last quarter.  Same stage buffer as
+// store_tile_staged.
+template <int NT>
+__device__ inline void store_tile_whole(float *win0, const f16v (&acc)[NT], float *stage, int h, int col, int lane,
+                                        float scale) {
+  constexpr int N = NT * 32, QF = 8 * N, NV = QF / 256;  // NV: 16-byte vectors per lane per quarter
+  const int delta = (int)((reinterpret_cast<uintptr_t>(win0) >> 2) & 3);
+  float *const g0 = win0 - delta;  // 16-byte aligned
+  float edge = 0.0f;  // lanes 4..7: block 0 of the tile; lanes 0..3: the floats past the last whole block
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    // this quarter's windows; their floats past index QF belong to the next
+    // quarter (which writes them again) or, for the last, to the tail block
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) stage[delta + (4 * h + j) * N + 32 * t + col] = acc[t][4 * q + j] * scale;
+    // the end of the previous quarter's last window (row 7, last delta samples)
+    if (q > 0 && h == 1 && col >= 32 - delta) stage[col - 32 + delta] = acc[NT - 1][4 * q - 1] * scale;
+    wave_sync_lds();
+    float *g = g0 + q * QF;
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+      const int m = lane + 64 * k;
+      if (q > 0 || m > 0 || delta == 0)  // block 0 of a misaligned tile is partial
+        *reinterpret_cast<f4a *>(g + 4 * m) = *reinterpret_cast<const f4a *>(stage + 4 * m);
+    }
+    if (q == 0 && lane >= 4 && lane < 8) edge = stage[lane - 4];
+    if (q == 3 && lane < 4) edge = stage[QF + lane];
+    wave_sync_lds();
+  }
+  const bool tail = lane < delta, head = delta > 0 && lane >= 4 + delta && lane < 8;
+  if (tail || head) g0[(tail ? 4 * QF : -4) + lane] = edge;
+}
+
 // Store output tile t (samples 32 t .. 32 t + 31 of every window) of a block
 // of up to 32 consecutive windows of one stream: win0 = first sample of the
 // block's window 0, rem = samples from there to the end of the block (window
@@ -350,6 +391,40 @@ __device__ inline void store_rows(float *win0, int N, const f16v &acc, int t, in
   }
 }
 
+
+// Chunk records (and per-stream scales) are read with vector loads, one dword
+// per lane, then moved to scalar registers with readlane.  A scalar load
+// would share its wait counter with LDS accesses and return out of order, so
+// the first LDS wait after it -- the decode loop's first lookup -- would stall
+// for the load's whole memory latency.  Vector loads retire in order with the
+// word loads and are waited for together with them.
+__device__ inline uint32_t load_meta_lane(const ChunkMeta *meta, int64_t c, int64_t n, int lane) {
+  return (c < n && lane < 16) ? reinterpret_cast<const uint32_t *>(meta + c)[lane] : 0u;
+}
+// The record whose dwords lanes 0..15 hold; c >= n (no record) gives
+// first_word = -1 and no windows.
+__device__ inline ChunkMeta meta_from_lanes(uint32_t d, bool valid) {
+  uint32_t w[16];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) w[i] = __builtin_amdgcn_readlane(d, i);
+  ChunkMeta m;
+  __builtin_memcpy(&m, w, sizeof(m));
+  if (!valid) {
+    m.first_word = -1;
+    m.n_windows = 0;
+  }
+  return m;
+}
+// gamma[3 s + lane] in lanes 0..2 (1 without scales).
+__device__ inline float load_gamma_lane(const float *gamma, int s, int lane) {
+  return (gamma && lane < 3) ? gamma[3 * (int64_t)s + lane] : 1.0f;
+}
+__device__ inline float lane_float(float v, int i) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), i));
+}
+// Wait for a lane-loaded value here (see settle_chunk_words).
+__device__ inline void settle_lane(uint32_t d) { asm volatile("" ::"v"(d) : "memory"); }
+__device__ inline void settle_lane(float d) { asm volatile("" ::"v"(d) : "memory"); }
 
 // Inclusive prefix sum across a 64-lane wavefront with DPP row shifts and row
 // broadcasts (no LDS round trips).

@@ -47,6 +47,20 @@ def test_fused_paper_quantizer_with_scales(N, E):
         check_parity(c, run_gpu(c, precision=prec, fused=True), tol=1e-5, check_symbols=False)
 
 
+@pytest.mark.parametrize("N", [32, 64, 128, 256])
+def test_whole_tile_stores_at_every_alignment(N):
+    # streams start at sample offsets 0, 1, 2, 3 (mod 4) and hold whole
+    # 32-window tiles, so tile stores meet every 16-byte misalignment; both
+    # entry points (split: dequant+IDCT from the symbol array)
+    T = 32 * N
+    lens = [1, 2 * T + 1, 3 * T + 1, T + 2, 2 * T + 3, 77]
+    assert [int(x) % 4 for x in np.cumsum([0] + lens[:-1])] == [0, 1, 2, 3, 1, 0]
+    kw = dict(step_f=1.0, step_c=8.0, T=16.0) if N == 256 else {}
+    c = build_case(_amp(N, **kw), ["eeg", "seismic", "power", "meteo"], lens, config_id=1900 + N)
+    for fused in (False, True):
+        check_parity(c, run_gpu(c, precision="fp16x2", fused=fused), tol=1e-5, check_symbols=not fused)
+
+
 def test_fused_flags_corrupt_streams_and_isolates_the_rest():
     from paper_2605_01086_amd import fptc as F
     lens = [4000, 5000, 6000, 7000, 3000]
