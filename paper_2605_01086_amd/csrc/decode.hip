@@ -101,7 +101,9 @@ __global__ void __launch_bounds__(1024) k_decode(const uint64_t *__restrict__ wo
       for (int k = lane; k < nblk; k += kWave) {
         const int lo = k * 16, hi2 = lo + 16;
         if (lo >= mis && hi2 <= mis + nbytes && sym_base - mis + hi2 <= n_symbols) {
-          *reinterpret_cast<uint4 *>(dst_al + lo) = *reinterpret_cast<const uint4 *>(buf + lo);
+          // non-temporal: whole 16-byte blocks of a contiguous stream
+          typedef uint32_t u4 __attribute__((ext_vector_type(4)));
+          __builtin_nontemporal_store(*reinterpret_cast<const u4 *>(buf + lo), reinterpret_cast<u4 *>(dst_al + lo));
         } else {
           for (int j = lo; j < hi2; ++j)
             if (j >= mis && j < mis + nbytes && sym_base + (j - mis) < n_symbols) dst_al[j] = buf[j];

@@ -339,8 +339,10 @@ __device__ inline void store_tile_staged(float *win0, const f16v (&acc)[NT], flo
 // last delta floats of quarter q - 1's windows.  Every block inside the tile
 // is then whole and leaves with one 16-byte store; only the tile's first and
 // last blocks are partial, and their floats (at most 3 + 3) leave together,
-// one per lane, after the last quarter.  Same stage buffer as
-// store_tile_staged.
+// one per lane, after the last quarter.  The whole blocks are non-temporal
+// stores: each instruction writes 1 KB of whole 64-byte lines, so nothing has
+// to be combined in L2, and the stream does not displace cached data.  Same
+// stage buffer as store_tile_staged.
 template <int NT>
 __device__ inline void store_tile_whole(float *win0, const f16v (&acc)[NT], float *stage, int h, int col, int lane,
                                         float scale) {
@@ -364,7 +366,7 @@ __device__ inline void store_tile_whole(float *win0, const f16v (&acc)[NT], floa
     for (int k = 0; k < NV; ++k) {
       const int m = lane + 64 * k;
       if (q > 0 || m > 0 || delta == 0)  // block 0 of a misaligned tile is partial
-        *reinterpret_cast<f4a *>(g + 4 * m) = *reinterpret_cast<const f4a *>(stage + 4 * m);
+        __builtin_nontemporal_store(*reinterpret_cast<const f4a *>(stage + 4 * m), reinterpret_cast<f4a *>(g + 4 * m));
     }
     if (q == 0 && lane >= 4 && lane < 8) edge = stage[lane - 4];
     if (q == 3 && lane < 4) edge = stage[QF + lane];
