@@ -21,7 +21,7 @@
 //   BF16X3: basis = hi + mid + lo in BF16, coefficients likewise.
 // The basis pieces live in LDS (rows padded by 16 bytes to spread banks), as do
 // the dequantization tables and each wave's tile of symbols; coefficients are
-// dequantized in registers from the symbols (tile_contract).
+// dequantized in registers from the symbols (tile_contract_emit).
 #include <hip/hip_runtime.h>
 
 #include "fptc_internal.h"
@@ -179,26 +179,27 @@ __global__ void __launch_bounds__(kThreads, NT >= 4 ? 2 : (NT == 2 ? 3 : 4)) k_d
       const int wr = tt * kTileWindows + col;
       const int valid = col < wt ? min(N, cm.out_len - wr * N) : 0;
       const int base = (col < wt ? col : wt - 1) * E;
-      f16v acc[NT];
-      tile_contract<PREC, NT>(acc, sb, base, h, col, S, E, valid > 0, Bs, RS, Rb + book * E,
-                              Tv + book * n_rows * 256, Tz + book * n_rows * 256, Pq + book * n_rows * 256, n_rows,
-                              gamma, g0, g1, g2);
-      if (tt == 0) {  // before this chunk's stores
-        settle_tile_syms(nx);
-        settle_lane(vm);
-        settle_lane(vgn);
-      }
       float *win0 = out + cm.out_base + (int64_t)tt * kTileWindows * N;
       const int rem = cm.out_len - tt * kTileWindows * N;
-      if (E == N) {  // stage through the consumed symbol tile
-        if (rem >= kTileWindows * N)
-          store_tile_whole<NT>(win0, acc, reinterpret_cast<float *>(sb) - 4, h, col, lane, oscale);
-        else
-          store_tile_staged<NT>(win0, acc, reinterpret_cast<float *>(sb) - 4, h, col, lane, rem, oscale);
-      } else {
+      auto emit = [&](const f16v (&acc)[NT]) {
+        if (tt == 0) {  // before this chunk's stores
+          settle_tile_syms(nx);
+          settle_lane(vm);
+          settle_lane(vgn);
+        }
+        if (E == N) {  // stage through the consumed symbol tile
+          if (rem >= kTileWindows * N)
+            store_tile_whole<NT>(win0, acc, reinterpret_cast<float *>(sb) - 4, h, col, lane, oscale);
+          else
+            store_tile_staged<NT>(win0, acc, reinterpret_cast<float *>(sb) - 4, h, col, lane, rem, oscale);
+        } else {
 #pragma unroll
-        for (int t = 0; t < NT; ++t) store_rows(win0, N, acc[t], t, h, col, rem, oscale);
-      }
+          for (int t = 0; t < NT; ++t) store_rows(win0, N, acc[t], t, h, col, rem, oscale);
+        }
+      };
+      tile_contract_emit<PREC, NT>(sb, base, h, col, S, E, valid > 0, Bs, RS, Rb + book * E,
+                                   Tv + book * n_rows * 256, Tz + book * n_rows * 256, Pq + book * n_rows * 256,
+                                   n_rows, gamma, g0, g1, g2, emit);
       wave_sync_lds();
     }
     settle_tile_syms(nx);

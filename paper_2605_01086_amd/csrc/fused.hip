@@ -151,22 +151,23 @@ __global__ void __launch_bounds__(64 * max_fused_waves(NT * 32)) k_fused(const u
         const int valid = wr < w_cnt ? min(N, cm.out_len - wr * N) : 0;
         // windows past the chunk read the last window's symbols (discarded)
         const int base = (wr < w_cnt ? wr : w_cnt - 1) * E;
-        f16v acc[NT];
-        tile_contract<PREC, NT>(acc, sb, base, h, col, S, E, valid > 0, Bs, RS, Rb + book * E,
-                                Tv + book * n_rows * 256, Tz + book * n_rows * 256, Pq + book * n_rows * 256, n_rows,
-                                gamma, g0, g1, g2);
         // the chunk's windows are consecutive in one stream
         float *win0 = out + cm.out_base + (int64_t)tt * kTileWindows * N;
         const int rem = cm.out_len - tt * kTileWindows * N;
-        if (E == N && wpc >= kTileWindows) {  // a quarter tile fits in the consumed symbol buffer
-          if (rem >= kTileWindows * N)
-            store_tile_whole<NT>(win0, acc, reinterpret_cast<float *>(sb) - 4, h, col, lane, oscale);
-          else
-            store_tile_staged<NT>(win0, acc, reinterpret_cast<float *>(sb) - 4, h, col, lane, rem, oscale);
-        } else {
+        auto emit = [&](const f16v (&acc)[NT]) {
+          if (E == N && wpc >= kTileWindows) {  // a quarter tile fits in the consumed symbol buffer
+            if (rem >= kTileWindows * N)
+              store_tile_whole<NT>(win0, acc, reinterpret_cast<float *>(sb) - 4, h, col, lane, oscale);
+            else
+              store_tile_staged<NT>(win0, acc, reinterpret_cast<float *>(sb) - 4, h, col, lane, rem, oscale);
+          } else {
 #pragma unroll
-          for (int t = 0; t < NT; ++t) store_rows(win0, N, acc[t], t, h, col, rem, oscale);
-        }
+            for (int t = 0; t < NT; ++t) store_rows(win0, N, acc[t], t, h, col, rem, oscale);
+          }
+        };
+        tile_contract_emit<PREC, NT>(sb, base, h, col, S, E, valid > 0, Bs, RS, Rb + book * E,
+                                     Tv + book * n_rows * 256, Tz + book * n_rows * 256, Pq + book * n_rows * 256,
+                                     n_rows, gamma, g0, g1, g2, emit);
       }
       wave_sync_lds();
     }

@@ -166,30 +166,34 @@ __device__ inline bool gather8(uint32_t s0, uint32_t s1, int k0, const uint32_t 
 // the k-step; tiles are tstride halves apart, pieces pstride halves apart.
 // Callers run the k-steps from the highest bins down so that the low bins --
 // the DC term in particular, often a large offset -- enter the FP32 sums last
-// and the partial sums stay small.
-template <int PREC, int NT>
+// and the partial sums stay small.  FIRST: acc holds nothing yet, and the
+// tile's first product takes a zero accumulator operand (no registers to
+// clear beforehand; the same sums).
+template <int PREC, int NT, bool FIRST = false>
 __device__ inline void mfma_step(f16v (&acc)[NT], const u8v (&a)[Traits<PREC>::kAPieces], const uint16_t *brow,
                                  int tstride, int pstride, bool any_rest) {
   using T = Traits<PREC>;
   constexpr int BP = T::kBPieces;
+  const f16v zero = {};
 #pragma unroll
   for (int t = 0; t < NT; ++t) {
     u8v bp[BP];
 #pragma unroll
     for (int p = 0; p < BP; ++p) bp[p] = *reinterpret_cast<const u8v *>(brow + t * tstride + p * pstride);
+    f16v c = FIRST ? zero : acc[t];
     if constexpr (BP == 3) {
-      acc[t] = mfma<T::kF16>(bp[2], a[0], acc[t]);
+      c = mfma<T::kF16>(bp[2], a[0], c);
       if (any_rest) {
-        acc[t] = mfma<T::kF16>(bp[1], a[1], acc[t]);
-        acc[t] = mfma<T::kF16>(bp[0], a[2], acc[t]);
+        c = mfma<T::kF16>(bp[1], a[1], c);
+        c = mfma<T::kF16>(bp[0], a[2], c);
       }
-      acc[t] = mfma<T::kF16>(bp[1], a[0], acc[t]);
-      if (any_rest) acc[t] = mfma<T::kF16>(bp[0], a[1], acc[t]);
+      c = mfma<T::kF16>(bp[1], a[0], c);
+      if (any_rest) c = mfma<T::kF16>(bp[0], a[1], c);
     } else if constexpr (BP == 2) {
-      if (any_rest) acc[t] = mfma<T::kF16>(bp[0], a[1], acc[t]);
-      acc[t] = mfma<T::kF16>(bp[1], a[0], acc[t]);
+      if (any_rest) c = mfma<T::kF16>(bp[0], a[1], c);
+      c = mfma<T::kF16>(bp[1], a[0], c);
     }
-    acc[t] = mfma<T::kF16>(bp[0], a[0], acc[t]);
+    acc[t] = mfma<T::kF16>(bp[0], a[0], c);
   }
 }
 
@@ -213,18 +217,39 @@ __device__ inline void stage_basis(uint16_t *Bs, const float *basis, int N, int 
 
 // One 32-window tile of a wavefront: acc[t] (output samples t*32 ..) of the
 // tile's windows from their symbols at sb[base + bin] in LDS.  k-steps run
-// from the highest bins down.  Without scales, with E a multiple of 16 and at
-// most two pieces, coefficients come from the pre-split table pq (the row
-// lookup compiled out when the book has one row); otherwise through
-// dequant8.  Lanes whose window is not
-// valid compute on the clamped window's symbols; only their lower-piece flag is
-// masked, so valid columns get exactly the general path's arithmetic.
-//   Bs: split basis [piece][n][RS]; rb/tv/tz/pq: this book's tables.
+// from the highest bins down.  Two forms:
+//  * contract_presplit: without scales, with E a multiple of 16 and at most
+//    two pieces, coefficients come from the pre-split table pq (MULTI_ROW:
+//    with the row lookup, else the book has one row);
+//  * contract_dequant: any case, through dequant8.
+// Lanes whose window is not valid compute on the clamped window's symbols;
+// only their lower-piece flag is masked, so valid columns get exactly the
+// general form's arithmetic.  Bs: split basis [piece][n][RS]; rb/tv/tz/pq:
+// this book's tables.
+template <int PREC, int NT, bool MULTI_ROW>
+__device__ inline void contract_presplit(f16v (&acc)[NT], const unsigned char *sb, int base, int h, int col, int S,
+                                         bool valid, const uint16_t *Bs, int RS, const uint8_t *rb,
+                                         const uint32_t *pq) {
+  constexpr int N = NT * 32, AP = Traits<PREC>::kAPieces;
+  const int KH = S * 8;
+  auto step = [&](int ss, auto first) {
+    const int k0 = h * KH + 8 * ss;
+    const uint2 u = *reinterpret_cast<const uint2 *>(sb + base + k0);
+    u8v a[AP];
+    const bool r = gather8<PREC, MULTI_ROW>(u.x, u.y, k0, pq, rb, a);
+    const bool any_rest = AP > 1 && __any(r && valid);
+    mfma_step<PREC, NT, decltype(first)::value>(acc, a, Bs + col * RS + k0, 32 * RS, N * RS, any_rest);
+  };
+  step(S - 1, std::true_type{});
+#pragma unroll 1
+  for (int ss = S - 2; ss >= 0; --ss) step(ss, std::false_type{});
+}
+
 template <int PREC, int NT>
-__device__ inline void tile_contract(f16v (&acc)[NT], const unsigned char *sb, int base, int h, int col, int S,
-                                     int E, bool valid, const uint16_t *Bs, int RS, const uint8_t *rb, const float *tv,
-                                     const uint8_t *tz, const uint32_t *pq, int n_rows, const float *gamma, float g0,
-                                     float g1, float g2) {
+__device__ inline void contract_dequant(f16v (&acc)[NT], const unsigned char *sb, int base, int h, int col, int S,
+                                        int E, bool valid, const uint16_t *Bs, int RS, const uint8_t *rb,
+                                        const float *tv, const uint8_t *tz, bool scaled, float g0, float g1,
+                                        float g2) {
   using T = Traits<PREC>;
   constexpr int N = NT * 32;
   constexpr int AP = T::kAPieces;
@@ -234,27 +259,6 @@ __device__ inline void tile_contract(f16v (&acc)[NT], const unsigned char *sb, i
   for (int t = 0; t < NT; ++t)
 #pragma unroll
     for (int r = 0; r < 16; ++r) acc[t][r] = 0.0f;
-  if constexpr (AP <= 2) {
-    if (!gamma && e_vec) {
-      auto run = [&](auto multi_row) {
-        constexpr bool MR = decltype(multi_row)::value;
-#pragma unroll 1
-        for (int ss = S - 1; ss >= 0; --ss) {
-          const int k0 = h * KH + 8 * ss;
-          const uint2 u = *reinterpret_cast<const uint2 *>(sb + base + k0);
-          u8v a[AP];
-          const bool r = gather8<PREC, MR>(u.x, u.y, k0, pq, rb, a);
-          const bool any_rest = AP > 1 && __any(r && valid);
-          mfma_step<PREC, NT>(acc, a, Bs + col * RS + k0, 32 * RS, N * RS, any_rest);
-        }
-      };
-      if (n_rows > 1)
-        run(std::true_type{});
-      else
-        run(std::false_type{});
-      return;
-    }
-  }
 #pragma unroll 1
   for (int ss = S - 1; ss >= 0; --ss) {
     const int k0 = h * KH + 8 * ss;
@@ -271,10 +275,36 @@ __device__ inline void tile_contract(f16v (&acc)[NT], const unsigned char *sb, i
       for (int j = 0; j < 8; ++j) sy[j] = sb[base + (k0 + j < E ? k0 + j : 0)];
     }
     u8v a[AP];
-    const bool r = dequant8<PREC>(sy, k0, E, valid, rb, tv, tz, gamma != nullptr, g0, g1, g2, a);
+    const bool r = dequant8<PREC>(sy, k0, E, valid, rb, tv, tz, scaled, g0, g1, g2, a);
     const bool any_rest = AP > 1 && __any(r);
     mfma_step<PREC, NT>(acc, a, Bs + col * RS + k0, 32 * RS, N * RS, any_rest);
   }
+}
+
+// Contract a tile with the form that applies and hand the result to emit
+// (each form keeps its own accumulators up to the stores).
+template <int PREC, int NT, typename Emit>
+__device__ inline void tile_contract_emit(const unsigned char *sb, int base, int h, int col, int S, int E, bool valid,
+                                          const uint16_t *Bs, int RS, const uint8_t *rb, const float *tv,
+                                          const uint8_t *tz, const uint32_t *pq, int n_rows, const float *gamma,
+                                          float g0, float g1, float g2, Emit &&emit) {
+  if constexpr (Traits<PREC>::kAPieces <= 2) {
+    if (!gamma && (E % 16) == 0) {
+      if (n_rows > 1) {
+        f16v acc[NT];
+        contract_presplit<PREC, NT, true>(acc, sb, base, h, col, S, valid, Bs, RS, rb, pq);
+        emit(acc);
+      } else {
+        f16v acc[NT];
+        contract_presplit<PREC, NT, false>(acc, sb, base, h, col, S, valid, Bs, RS, rb, pq);
+        emit(acc);
+      }
+      return;
+    }
+  }
+  f16v acc[NT];
+  contract_dequant<PREC, NT>(acc, sb, base, h, col, S, E, valid, Bs, RS, rb, tv, tz, gamma != nullptr, g0, g1, g2);
+  emit(acc);
 }
 
 typedef float f4u __attribute__((ext_vector_type(4), aligned(4)));  // 16 bytes, 4-byte aligned
