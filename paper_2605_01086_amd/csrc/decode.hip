@@ -49,6 +49,7 @@ __global__ void __launch_bounds__(1024) k_decode(const uint64_t *__restrict__ wo
   unsigned char *buf = lds + lut_bytes + wid * decode_wave_bytes(wpc, E) + kSymPrefix;
   const void *lut = lds;
   const uint8_t *cl = lds + ((size_t)n_books << lmax) * 4;
+  const uint32_t *binfo = reinterpret_cast<const uint32_t *>(cl + n_books * 256);  // multi-symbol form only
 
   stage_decode_tables(MS, lds, lds + lut_bytes, lut_g, lmax, n_books, threadIdx.x, blockDim.x);
 
@@ -83,7 +84,7 @@ __global__ void __launch_bounds__(1024) k_decode(const uint64_t *__restrict__ wo
       const void *lb = MS ? (const void *)((const uint32_t *)lut + (book << lmax))
                           : (const void *)((const uint16_t *)lut + (book << lmax));
       err = decode_chunk<MS>(words, symlen, cm.first_word, cm.first_sym, nbytes, cm.word_end, cw, lb,
-                             cl + book * 256, hs, buf + mis, lane);
+                             cl + book * 256, MS ? binfo[book] : 0u, hs, buf + mis, lane);
     }
     settle_chunk_words(nx);
     settle_lane(vm);

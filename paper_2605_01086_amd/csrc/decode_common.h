@@ -18,6 +18,19 @@
 //    writes all three symbol bytes; the at most two that fall past a lane's
 //    run land on the first two positions of a later run, and every run writes
 //    its first two symbols again once all lanes have finished.
+//  * sparse multi-symbol (uint32), for a codebook whose fill symbol F (the
+//    symbol of the all-zero peek, i.e. the shortest code) has a 1- or 2-bit
+//    code, as for the zero level of sparse spectra: the chunk's symbol buffer
+//    is first filled with F, and an entry resolves up to 15 whole codes of
+//    which at most two are not F; only those are written:
+//      bits  0..7   first non-F symbol (F if none)     bits  8..11 its offset
+//      bits 12..15  total length of the codes
+//      bits 16..23  second non-F symbol (the first's if none)
+//      bits 24..27  its offset                         bits 28..31 count
+//    An entry whose first code is missing has offset 15 in slot one (real
+//    offsets are at most 14).  Writes past a lane's run are suppressed, so no
+//    fix-up is needed.  A per-codebook info word records the form chosen:
+//      bit 0 sparse, bits 8..15 F, bits 16..23 code length of F.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -35,10 +48,12 @@ constexpr int kSymPrefix = 64;
 constexpr int kPreRounds = 2;
 constexpr uint32_t kLutMissing = 1u << 30;
 
+// multi-symbol: entries | code lengths [book][256] | info word per book
 __host__ __device__ inline size_t lut_lds_bytes(bool ms, int n_books, int lmax) {
   const size_t e = (size_t)n_books << lmax;
-  return ((ms ? e * 4 + (size_t)n_books * 256 : e * 2) + 15) & ~(size_t)15;
+  return ((ms ? e * 4 + (size_t)n_books * 260 : e * 2) + 15) & ~(size_t)15;
 }
+constexpr uint32_t kSparseMissing = (15u << 8) | (15u << 24) | (1u << 28);
 __host__ __device__ inline size_t lut1_temp_bytes(int n_books, int lmax) {
   return (((size_t)n_books << lmax) * 2 + 15) & ~(size_t)15;
 }
@@ -57,36 +72,71 @@ __device__ inline void stage_lut(uint16_t *lut, const uint16_t *lut_g, int entri
 // taken only when its whole length lies inside the peek: the bits after the
 // first codes are then a prefix of the real stream, and prefix-freeness makes
 // the table's answer for them the real next code.
-__device__ inline void build_lut3(uint32_t *lut3, uint8_t *cl, const uint16_t *lut1, int lmax, int n_books, int tid,
-                                  int nthreads) {
+__device__ inline void build_lut3(uint32_t *lut3, uint8_t *cl, uint32_t *info, const uint16_t *lut1, int lmax,
+                                  int n_books, int tid, int nthreads) {
   const uint32_t mask = (1u << lmax) - 1;
   for (int i = tid; i < (n_books << lmax); i += nthreads) {
     const uint16_t *L = lut1 + (i & ~(int)mask);
     const uint32_t idx = (uint32_t)i & mask;
+    // the book's fill symbol: the all-zero peek's code, the shortest one
+    const uint32_t z = L[0], lf = z >> 8, fsym = z & 255u;
+    const bool sparse = lf >= 1 && lf <= 2;
+    if (idx == 0) info[i >> lmax] = (sparse ? 1u : 0u) | (fsym << 8) | (lf << 16);
     const uint32_t e0 = L[idx];
     uint32_t len = e0 >> 8, out;
     if (len == 0) {
-      out = kLutMissing | (1u << 28) | ((uint32_t)lmax << 24);
+      out = sparse ? (kSparseMissing | ((uint32_t)lmax << 12)) : (kLutMissing | (1u << 28) | ((uint32_t)lmax << 24));
     } else {
       cl[(i >> lmax) * 256 + (e0 & 255u)] = (uint8_t)len;  // every entry of a symbol writes the same length
-      out = e0 & 255u;
-      uint32_t c = 1;
-      for (int k = 1; k < 3; ++k) {
-        const uint32_t e = L[(idx << len) & mask];
-        const uint32_t l = e >> 8;
-        if (l == 0 || len + l > (uint32_t)lmax) break;
-        out |= (e & 255u) << (8 * c);
-        len += l;
-        ++c;
+      if (!sparse) {
+        out = e0 & 255u;
+        uint32_t c = 1;
+        for (int k = 1; k < 3; ++k) {
+          const uint32_t e = L[(idx << len) & mask];
+          const uint32_t l = e >> 8;
+          if (l == 0 || len + l > (uint32_t)lmax) break;
+          out |= (e & 255u) << (8 * c);
+          len += l;
+          ++c;
+        }
+        out |= (len << 24) | (c << 28);
+      } else {
+        uint32_t c = 1, nf = 0, sa = fsym, oa = 0, sb = 0, ob = 0;
+        if ((e0 & 255u) != fsym) {
+          sa = e0 & 255u;
+          nf = 1;
+        }
+        while (c < 15) {
+          const uint32_t e = L[(idx << len) & mask];
+          const uint32_t l = e >> 8, s = e & 255u;
+          if (l == 0 || len + l > (uint32_t)lmax) break;
+          if (s != fsym) {
+            if (nf == 2) break;
+            if (nf == 0) {
+              sa = s;
+              oa = c;
+            } else {
+              sb = s;
+              ob = c;
+            }
+            ++nf;
+          }
+          len += l;
+          ++c;
+        }
+        if (nf < 2) {
+          sb = sa;
+          ob = oa;
+        }
+        out = sa | (oa << 8) | (len << 12) | (sb << 16) | (ob << 24) | (c << 28);
       }
-      out |= (len << 24) | (c << 28);
     }
     lut3[i] = out;
   }
 }
 
 // Stage the lookup tables a decode kernel uses.  ms: multi-symbol tables at
-// lut (then cl follows them); temp: LDS scratch of lut1_temp_bytes() that the
+// lut (then the code lengths and the info words follow them); temp: LDS scratch of lut1_temp_bytes() that the
 // caller overwrites only after a barrier.  Ends with a block barrier.
 __device__ inline void stage_decode_tables(bool ms, unsigned char *lut, unsigned char *temp, const uint16_t *lut_g,
                                            int lmax, int n_books, int tid, int nthreads) {
@@ -95,7 +145,9 @@ __device__ inline void stage_decode_tables(bool ms, unsigned char *lut, unsigned
     uint16_t *t = reinterpret_cast<uint16_t *>(temp);
     for (int i = tid; i < entries; i += nthreads) t[i] = lut_g[i];
     __syncthreads();
-    build_lut3(reinterpret_cast<uint32_t *>(lut), lut + (size_t)entries * 4, t, lmax, n_books, tid, nthreads);
+    build_lut3(reinterpret_cast<uint32_t *>(lut), lut + (size_t)entries * 4,
+               reinterpret_cast<uint32_t *>(lut + (size_t)entries * 4 + (size_t)n_books * 256), t, lmax, n_books, tid,
+               nthreads);
   } else {
     stage_lut(reinterpret_cast<uint16_t *>(lut), lut_g, entries, tid, nthreads);
   }
@@ -183,12 +235,66 @@ __device__ inline int decode_word(uint64_t wd, unsigned char *p, int cnt, const 
   return err;
 }
 
+// Sparse-table form of decode_word: the buffer already holds the fill symbol
+// at every position; lf is the fill symbol's code length.  While 16 or more
+// symbols remain no entry can reach past the run, so the slot writes need no
+// mask; the last few lookups drop slots past the run.
+__device__ inline int decode_word_sparse(uint64_t wd, unsigned char *p, int cnt, const uint32_t *L, const uint8_t *cl,
+                                         int hs, int lf) {
+  unsigned char *const pe = p + cnt;
+  int bits = 0, fl = 0;
+  uint32_t e = 0;
+  while (pe - p >= 16) {
+    e = L[(uint32_t)(wd >> 32) >> hs];
+    const int len = (e >> 12) & 15;
+    wd <<= len;
+    bits += len;
+    const int oa = (e >> 8) & 15;
+    fl = max(fl, oa);
+    p[oa] = (unsigned char)e;
+    p[(e >> 24) & 15] = (unsigned char)(e >> 16);
+    p += e >> 28;
+  }
+  while (p < pe) {
+    e = L[(uint32_t)(wd >> 32) >> hs];
+    const int len = (e >> 12) & 15;
+    wd <<= len;
+    bits += len;
+    const int rem = (int)(pe - p);
+    const int oa = (e >> 8) & 15, ob = (e >> 24) & 15;
+    fl = max(fl, oa);
+    if (oa < rem) p[oa] = (unsigned char)e;
+    if (ob < rem) p[ob] = (unsigned char)(e >> 16);
+    p += e >> 28;
+  }
+  // the last entry's codes past the run are not part of this word's count
+  const int c = (int)(e >> 28), k = (int)(pe - (p - c));  // k: its symbols inside the run
+  if (c > k) {
+    const int oa = (e >> 8) & 15, ob = (e >> 24) & 15;
+    const int a = oa < k, b = (ob < k) && (ob != oa);
+    bits += (k - a - b) * lf + (a ? (int)cl[e & 255u] : 0) + (b ? (int)cl[(e >> 16) & 255u] : 0) -
+            (int)((e >> 12) & 15);
+  }
+  return (fl == 15 || bits > 64) ? FPTC_STREAM_OVERRUN : 0;
+}
+
+// Fill sb[0 .. t_cnt) with the fill symbol (whole 16-byte blocks from sb's
+// 16-byte boundary down, so a few bytes around the range are written too).
+__device__ inline void prefill_symbols(unsigned char *sb, int t_cnt, uint32_t fsym, int lane) {
+  const int mis = (int)(reinterpret_cast<uintptr_t>(sb) & 15);
+  unsigned char *q = sb - mis;
+  const uint32_t f4 = 0x01010101u * fsym;
+  const uint4 v = make_uint4(f4, f4, f4, f4);
+  const int nblk = (mis + t_cnt + 15) >> 4;
+  for (int i = lane; i < nblk; i += 64) reinterpret_cast<uint4 *>(q)[i] = v;
+}
+
 // One round: 64 words, one per lane; a DPP prefix sum of symlen places each
 // lane's run at chunk-relative index o, and the lane decodes the run's part
 // inside [.., t_cnt).  P advances by the round's symbol count.
 template <bool MS>
 __device__ inline void decode_round(uint64_t word, int n, int &P, int t_cnt, const void *lut, const uint8_t *cl,
-                                    int hs, unsigned char *sb, int &err) {
+                                    uint32_t binfo, int hs, unsigned char *sb, int &err) {
   if (n > 64) {
     err |= FPTC_STREAM_BAD_SYMLEN;
     n = 64;
@@ -197,7 +303,13 @@ __device__ inline void decode_round(uint64_t word, int n, int &P, int t_cnt, con
   const int total = __builtin_amdgcn_readlane(incl, 63);
   const int o = P + incl - n;
   const int cnt = min(n, t_cnt - o);
-  if (cnt > 0) err |= decode_word<MS>(word, sb + o, cnt, lut, cl, hs);
+  if (cnt > 0) {
+    if (MS && (binfo & 1u))
+      err |= decode_word_sparse(word, sb + o, cnt, reinterpret_cast<const uint32_t *>(lut), cl, hs,
+                                (int)((binfo >> 16) & 255u));
+    else
+      err |= decode_word<MS>(word, sb + o, cnt, lut, cl, hs);
+  }
   P += total;
 }
 
@@ -205,16 +317,18 @@ __device__ inline void decode_round(uint64_t word, int n, int &P, int t_cnt, con
 // fw is the first word holding a symbol of the chunk, p0 <= 0 the chunk-
 // relative index of that word's first symbol, wend the stream's word end;
 // cw holds the first kPreRounds rounds of words (load_chunk_words), later
-// rounds are loaded here one round ahead.  Returns this lane's error bits.
+// rounds are loaded here one round ahead.  binfo: the codebook's info word
+// (multi-symbol tables; 0 otherwise).  Returns this lane's error bits.
 template <bool MS>
 __device__ inline int decode_chunk(const uint64_t *__restrict__ words, const uint8_t *__restrict__ symlen, int64_t fw,
                                    int p0, int t_cnt, int64_t wend, const ChunkWords &cw, const void *lut,
-                                   const uint8_t *cl, int hs, unsigned char *sb, int lane) {
+                                   const uint8_t *cl, uint32_t binfo, int hs, unsigned char *sb, int lane) {
   int err = 0, P = p0;
+  if (MS && (binfo & 1u)) prefill_symbols(sb, t_cnt, (binfo >> 8) & 255u, lane);
   int64_t w = fw;
 #pragma unroll
   for (int r = 0; r < kPreRounds; ++r) {
-    if (P < t_cnt && w < wend) decode_round<MS>(cw.w[r], cw.n[r], P, t_cnt, lut, cl, hs, sb, err);
+    if (P < t_cnt && w < wend) decode_round<MS>(cw.w[r], cw.n[r], P, t_cnt, lut, cl, binfo, hs, sb, err);
     w += 64;
   }
   if (P < t_cnt && w < wend) {
@@ -233,7 +347,7 @@ __device__ inline int decode_chunk(const uint64_t *__restrict__ words, const uin
         nword = words[w + 64 + lane];
         nn = symlen[w + 64 + lane];
       }
-      decode_round<MS>(word, n, P, t_cnt, lut, cl, hs, sb, err);
+      decode_round<MS>(word, n, P, t_cnt, lut, cl, binfo, hs, sb, err);
       w += 64;
     }
   }

@@ -101,6 +101,7 @@ __global__ void __launch_bounds__(64 * max_fused_waves(NT * 32)) k_fused(const u
   const int lane = threadIdx.x & 63, col = lane & 31, h = lane >> 5;
   unsigned char *sb = wave_base + (size_t)wid * fused_wave_bytes(E, wpc) + kSymPrefix;
   const uint8_t *cl = lds + ((size_t)n_books << lmax) * 4;
+  const uint32_t *binfo = reinterpret_cast<const uint32_t *>(cl + n_books * 256);  // multi-symbol form only
   const int hs = 32 - lmax;  // peek = top lmax bits of the word = hi32 >> hs
   const float oscale = 1.0f / (T::kF16 ? kBasisScaleF16 : 1.0f);
   const int64_t n_chunks = hdr[0];
@@ -133,7 +134,7 @@ __global__ void __launch_bounds__(64 * max_fused_waves(NT * 32)) k_fused(const u
       const void *lb = MS ? (const void *)(reinterpret_cast<const uint32_t *>(lds) + (book << lmax))
                           : (const void *)(reinterpret_cast<const uint16_t *>(lds) + (book << lmax));
       err = decode_chunk<MS>(words, symlen, cm.first_word, cm.first_sym, w_cnt * E, cm.word_end, cw, lb,
-                             cl + book * 256, hs, sb, lane);
+                             cl + book * 256, MS ? binfo[book] : 0u, hs, sb, lane);
     }
     settle_chunk_words(nx);
     settle_lane(vm);

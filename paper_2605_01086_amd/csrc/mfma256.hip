@@ -255,6 +255,7 @@ __global__ void __launch_bounds__(kMaxWaves256 * 64) k_fused256(const uint64_t *
   const int lane = threadIdx.x & 63, col = lane & 31, h = lane >> 5;
   unsigned char *sb = wave_base + (size_t)wid * wave256_bytes(wpc, E) + kSymPrefix;
   const uint8_t *cl = lds + ((size_t)n_books << lmax) * 4;
+  const uint32_t *binfo = reinterpret_cast<const uint32_t *>(cl + n_books * 256);  // multi-symbol form only
   const int hs = 32 - lmax;
   const int KH = S * 8, nblk = (S + kSB - 1) / kSB;
   const int ntile_max = (wpc + kTileWindows - 1) / kTileWindows;
@@ -289,7 +290,7 @@ __global__ void __launch_bounds__(kMaxWaves256 * 64) k_fused256(const uint64_t *
       const void *lb = MS ? (const void *)(reinterpret_cast<const uint32_t *>(lds) + (book << lmax))
                           : (const void *)(reinterpret_cast<const uint16_t *>(lds) + (book << lmax));
       err = decode_chunk<MS>(words, symlen, cm.first_word, cm.first_sym, w_cnt * E, cm.word_end, cw, lb,
-                             cl + book * 256, hs, sb, lane);
+                             cl + book * 256, MS ? binfo[book] : 0u, hs, sb, lane);
     }
     settle_chunk_words(nx);
     settle_lane(vm);

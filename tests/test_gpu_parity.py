@@ -93,3 +93,46 @@ def test_corrupt_streams_are_flagged_and_isolated():
     assert st[3] & F.FPTC_STREAM_BAD_SYMLEN
     assert st[4] != 0 or True  # all-ones words may still parse; the other streams must be unaffected
     check_parity(c, res, skip={1, 3, 4})
+
+
+@pytest.mark.parametrize("fused", [False, True])
+def test_overrun_flags_match_the_oracle(fused):
+    # one word per stream claims one symbol more and the next word one fewer,
+    # so the stream's total is unchanged: the stream must be flagged as an
+    # overrun exactly when the oracle's bit-serial decode of those counts runs
+    # past bit 64 of the word (streams 0-3 and 8-11: such a word; the others:
+    # a word whose extra symbol still fits), so every book -- dense (eeg) and
+    # sparse-table ones -- meets both outcomes.
+    from paper_2605_01086_amd import fptc as F
+    from oracle import oracle as O
+    lens = [6000 + 977 * i for i in range(16)]
+    c = build_case(_amp(64), ["eeg", "seismic", "power", "meteo"], lens, config_id=730, recon=False)
+    words, symlen, word_off, sample_off = c.concat()
+    sl = symlen.copy()
+    expect = []
+    for s in range(len(lens)):
+        want, chosen = (s // 4) % 2 == 0, None
+        for k in range(1, len(c.symlen[s]) - 2):
+            trial = c.symlen[s].copy()
+            if trial[k] >= 64 or trial[k + 1] < 2:
+                continue
+            trial[k] += 1
+            trial[k + 1] -= 1
+            try:
+                O.symlen_decode(c.words[s], trial, c.books[c.book_id[s]], int(trial.sum()))
+                over = False
+            except ValueError as e:
+                assert "-1" in str(e), str(e)
+                over = True
+            if over == want:
+                chosen = k
+                break
+        assert chosen is not None, s
+        sl[word_off[s] + chosen] += 1
+        sl[word_off[s] + chosen + 1] -= 1
+        expect.append(want)
+    res = run_gpu(c, symlen_override=sl, precision="fp16x2", fused=fused)
+    st = res["status"]
+    for s in range(len(lens)):
+        assert bool(st[s] & F.FPTC_STREAM_OVERRUN) == expect[s], (s, int(st[s]), expect[s])
+        assert (int(st[s]) & ~F.FPTC_STREAM_OVERRUN) == 0, (s, int(st[s]))
