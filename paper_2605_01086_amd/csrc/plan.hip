@@ -54,44 +54,99 @@ __device__ inline T block_excl_scan(T v, T *lds, T &total) {
 // One workgroup: per-stream window, chunk and symlen-segment counts, their
 // exclusive prefix sums, header validation, and the segment -> stream map.
 // Segments are kSegWords words on a 16-word grid aligned down from the
-// stream's first word.
+// stream's first word.  Each thread takes kStreamsPerThread consecutive
+// streams (all their offsets loaded at once), so a batch of up to
+// kPlanThreads * kStreamsPerThread streams needs one pass of block scans.
+constexpr int kStreamsPerThread = 4;
 __global__ void __launch_bounds__(kPlanThreads) k_plan_streams(fptc_batch b, int N, int E, int wpc,
                                                                int64_t *hdr, int64_t *win_off, int64_t *chunk_off,
                                                                int64_t *seg_off, int32_t *seg_stream,
                                                                int64_t seg_cap, int32_t *status) {
   __shared__ int64_t lds[kPlanThreads / kWave + 1];
+  constexpr int K = kStreamsPerThread;
+  __shared__ int64_t seg_at[kPlanThreads * K + 1];  // this pass's streams: first segment of each, then the end
   const int n = b.n_streams;
   const int64_t win_cap = b.n_symbols / E;
   int64_t carry_w = 0, carry_c = 0, carry_g = 0;
-  for (int base = 0; base < n; base += kPlanThreads) {
-    const int s = base + threadIdx.x;
-    int64_t nw = 0, w0 = 0, w1 = 0;
-    int flag = 0;
-    if (s < n) {
-      const int64_t s0 = b.sample_off[s], s1 = b.sample_off[s + 1];
-      w0 = b.word_off[s];
-      w1 = b.word_off[s + 1];
-      if (s0 < 0 || s1 < s0 || s1 > b.n_samples || w0 < 0 || w1 < w0 || w1 > b.n_words) flag = FPTC_STREAM_BAD_HEADER;
-      else nw = (s1 - s0 + N - 1) / N;
+  for (int base = 0; base < n; base += kPlanThreads * K) {
+    const int s0 = base + threadIdx.x * K;
+    int64_t so[K + 1], wo[K + 1];
+#pragma unroll
+    for (int k = 0; k <= K; ++k) {
+      const int s = s0 + k < n ? s0 + k : n;
+      so[k] = b.sample_off[s];
+      wo[k] = b.word_off[s];
+    }
+    int64_t nw[K], nc[K], ng[K];
+    int flag[K];
+    int64_t tw = 0;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      flag[k] = 0;
+      nw[k] = 0;
+      if (s0 + k < n) {
+        if (so[k] < 0 || so[k + 1] < so[k] || so[k + 1] > b.n_samples || wo[k] < 0 || wo[k + 1] < wo[k] ||
+            wo[k + 1] > b.n_words)
+          flag[k] = FPTC_STREAM_BAD_HEADER;
+        else
+          nw[k] = (so[k + 1] - so[k] + N - 1) / N;
+      }
+      tw += nw[k];
     }
     int64_t tot;
-    const int64_t wo = carry_w + block_excl_scan<int64_t, kPlanThreads>(nw, lds, tot);
+    int64_t w_at = carry_w + block_excl_scan<int64_t, kPlanThreads>(tw, lds, tot);
     carry_w += tot;
-    if (s < n && !flag && (wo + nw) > win_cap) flag = FPTC_STREAM_BAD_HEADER;
-    const int64_t nc = flag ? 0 : (nw + wpc - 1) / wpc;
-    const int64_t co = carry_c + block_excl_scan<int64_t, kPlanThreads>(nc, lds, tot);
-    carry_c += tot;
-    const int64_t a0 = w0 & ~(int64_t)15;
-    const int64_t ng = (flag || nc == 0 || w1 <= w0) ? 0 : (w1 - a0 + kSegWords - 1) / kSegWords;
-    const int64_t go = carry_g + block_excl_scan<int64_t, kPlanThreads>(ng, lds, tot);
-    carry_g += tot;
-    if (s < n) {
-      win_off[s] = wo;
-      chunk_off[s] = co;
-      seg_off[s] = go;
-      if (status) status[s] = flag;
-      for (int64_t g = go; g < go + ng && g < seg_cap; ++g) seg_stream[g] = s;
+    int64_t tc = 0, tg = 0;
+    int64_t wx[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      wx[k] = w_at;
+      if (s0 + k < n && !flag[k] && w_at + nw[k] > win_cap) flag[k] = FPTC_STREAM_BAD_HEADER;
+      w_at += nw[k];
+      nc[k] = flag[k] ? 0 : (nw[k] + wpc - 1) / wpc;
+      const int64_t a0 = wo[k] & ~(int64_t)15;
+      ng[k] = (flag[k] || nc[k] == 0 || wo[k + 1] <= wo[k]) ? 0 : (wo[k + 1] - a0 + kSegWords - 1) / kSegWords;
+      tc += nc[k];
+      tg += ng[k];
     }
+    int64_t c_at = carry_c + block_excl_scan<int64_t, kPlanThreads>(tc, lds, tot);
+    carry_c += tot;
+    int64_t g_at = carry_g + block_excl_scan<int64_t, kPlanThreads>(tg, lds, tot);
+    carry_g += tot;
+    const int64_t g_pass = carry_g - tot;  // this pass's first segment
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int s = s0 + k;
+      if (s < n) {
+        win_off[s] = wx[k];
+        chunk_off[s] = c_at;
+        seg_off[s] = g_at;
+        if (status) status[s] = flag[k];
+      }
+      seg_at[threadIdx.x * K + k] = g_at;  // past n: the pass's end
+      c_at += nc[k];
+      g_at += ng[k];
+    }
+    if (threadIdx.x == 0) seg_at[kPlanThreads * K] = carry_g;
+    __syncthreads();
+    // segment -> stream map: each thread a contiguous range of this pass's
+    // segments, its first stream by binary search, then walking forward
+    const int64_t per = (tot + kPlanThreads - 1) / kPlanThreads;
+    const int64_t g_lo = g_pass + (int64_t)threadIdx.x * per, g_hi = min(g_lo + per, carry_g);
+    if (g_lo < g_hi) {
+      int lo = 0, hi = kPlanThreads * K - 1;  // last local stream whose first segment is <= g_lo
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (seg_at[mid] <= g_lo) lo = mid;
+        else hi = mid - 1;
+      }
+      int i = lo;
+      for (int64_t g = g_lo; g < g_hi && g < seg_cap; ++g) {
+        while (seg_at[i + 1] <= g) ++i;
+        seg_stream[g] = base + i;
+      }
+    }
+    __syncthreads();
   }
   if (threadIdx.x == 0) {
     win_off[n] = carry_w;
@@ -170,8 +225,8 @@ __global__ void __launch_bounds__(kScanThreads) k_plan_seg_sums(fptc_batch b, co
                                                                 int32_t *seg_sum, int32_t *status) {
   __shared__ int lds[kScanThreads / kWave];
   const int64_t g = blockIdx.x;
+  const int s = seg_stream[g];  // read with the header (in bounds; used once g is known to be valid)
   if (g >= hdr[2]) return;
-  const int s = seg_stream[g];
   if (seg_off[s + 1] > hdr[3]) return;  // the stream's segments did not fit (flagged)
   SegWords sw;
   const int bad = load_seg_words(b, g, seg_off, seg_stream, s, sw);
@@ -256,8 +311,9 @@ __global__ void __launch_bounds__(kScanThreads) k_plan_seg_chunks(fptc_batch b, 
                                                                   const int64_t *seg_base, ChunkMeta *meta) {
   __shared__ int lds[kScanThreads / kWave];
   const int64_t g = blockIdx.x;
+  const int s = seg_stream[g];  // read with the header (in bounds; used once g is known to be valid)
+  const int64_t gb = seg_base[g];
   if (g >= hdr[2]) return;
-  const int s = seg_stream[g];
   if (seg_off[s + 1] > hdr[3]) return;  // the stream's segments did not fit (flagged)
   SegWords sw;
   load_seg_words(b, g, seg_off, seg_stream, s, sw);
@@ -268,7 +324,7 @@ __global__ void __launch_bounds__(kScanThreads) k_plan_seg_chunks(fptc_batch b, 
   const int ex = block_excl_scan_dpp(sum, lds, tot);
   const int64_t c0 = chunk_off[s], nc = chunk_off[s + 1] - c0;
   const int64_t cb = (int64_t)wpc * E;  // symbols per chunk
-  int64_t p = seg_base[g] + ex;
+  int64_t p = gb + ex;
   // the boundaries inside this thread's words, from the first at or after p
   int64_t m = (p + cb - 1) / cb;
   int64_t mb = m * cb;
