@@ -19,16 +19,21 @@ constexpr int kTileWindows = 32;  // windows per MFMA tile (one 32x32 output blo
 
 // Everything a wavefront needs to decode one chunk, written by the plan.
 struct ChunkMeta {
+  // written together, as one 16-byte group, by the plan's chunk-start pass
   int64_t first_word;  // global index of the first word holding a symbol of the chunk; -1 = skip
-  int64_t word_end;    // end (exclusive) of the chunk's words
+  int32_t first_sym;   // chunk-relative index of the first word's first symbol (<= 0)
+  int32_t last;        // 1 for a stream's last chunk
+  // The chunk's words end at the next chunk's first word (inclusive when that
+  // chunk starts inside it); a stream's last chunk ends at word_end, the end
+  // of the stream's words.
+  int64_t word_end;
   int64_t sym_base;    // global index of the chunk's first decoded symbol
   int64_t out_base;    // global index of the chunk's first output sample
-  int32_t first_sym;   // chunk-relative index of the first word's first symbol (<= 0)
   int32_t n_windows;   // windows in the chunk
   int32_t out_len;     // output samples of the chunk
   int32_t stream;
   int32_t book;
-  int32_t pad[3];
+  int32_t pad[2];
 };
 static_assert(sizeof(ChunkMeta) == 64, "ChunkMeta is one 64-byte record");
 

@@ -430,17 +430,25 @@ __device__ inline void store_rows(float *win0, int N, const f16v &acc, int t, in
 // the first LDS wait after it -- the decode loop's first lookup -- would stall
 // for the load's whole memory latency.  Vector loads retire in order with the
 // word loads and are waited for together with them.
+// Lanes 0..15: the dwords of record c; lanes 16..18: the first word and
+// first symbol of record c + 1 (all ones when there is none).
 __device__ inline uint32_t load_meta_lane(const ChunkMeta *meta, int64_t c, int64_t n, int lane) {
-  return (c < n && lane < 16) ? reinterpret_cast<const uint32_t *>(meta + c)[lane] : 0u;
+  if (c >= n || lane >= 19) return 0u;
+  if (lane >= 16 && c + 1 >= n) return 0xffffffffu;
+  return reinterpret_cast<const uint32_t *>(meta + c)[lane];
 }
-// The record whose dwords lanes 0..15 hold; c >= n (no record) gives
-// first_word = -1 and no windows.
+// The record whose dwords lanes 0..18 hold (load_meta_lane), its word_end
+// resolved from the next record unless it is its stream's last chunk or the
+// next chunk has no start; valid = false (no record) gives first_word = -1
+// and no windows.
 __device__ inline ChunkMeta meta_from_lanes(uint32_t d, bool valid) {
-  uint32_t w[16];
+  uint32_t w[19];
 #pragma unroll
-  for (int i = 0; i < 16; ++i) w[i] = __builtin_amdgcn_readlane(d, i);
+  for (int i = 0; i < 19; ++i) w[i] = __builtin_amdgcn_readlane(d, i);
   ChunkMeta m;
   __builtin_memcpy(&m, w, sizeof(m));
+  const int64_t nfw = (int64_t)(((uint64_t)w[17] << 32) | w[16]);
+  if (!m.last && nfw >= 0) m.word_end = nfw + ((int32_t)w[18] < 0 ? 1 : 0);
   if (!valid) {
     m.first_word = -1;
     m.n_windows = 0;

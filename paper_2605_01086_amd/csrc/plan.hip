@@ -271,15 +271,16 @@ __global__ void __launch_bounds__(kScanThreads) k_plan_stream_scan(fptc_batch b,
       const int64_t nwc = nw - wb < wpc ? nw - wb : wpc;
       const int64_t ol = L - wb * N < nwc * N ? L - wb * N : nwc * N;
       cm.first_word = -1;
+      cm.first_sym = 0;
+      cm.last = i == nc - 1;
       cm.word_end = w1;
       cm.sym_base = win_off[s] * E + wb * E;
       cm.out_base = so + wb * N;
-      cm.first_sym = 0;
       cm.n_windows = (int32_t)nwc;
       cm.out_len = (int32_t)ol;
       cm.stream = s;
       cm.book = bk;
-      cm.pad[0] = cm.pad[1] = cm.pad[2] = 0;
+      cm.pad[0] = cm.pad[1] = 0;
       meta[c0 + i] = cm;
     }
   }
@@ -303,7 +304,7 @@ __global__ void __launch_bounds__(kScanThreads) k_plan_stream_scan(fptc_batch b,
 // One workgroup per segment: exclusive scan of its words' symlen on top of
 // the segment's base; every word whose symbol range [p, p + symlen) holds the
 // first symbol of a chunk (a multiple of wpc * E) becomes that chunk's first
-// word, and the chunk before it ends at that word (inclusive when the chunk
+// word (the chunk before it ends at that word, inclusive when the chunk
 // starts inside the word).
 __global__ void __launch_bounds__(kScanThreads) k_plan_seg_chunks(fptc_batch b, int E, int wpc, const int64_t *hdr,
                                                                   const int64_t *chunk_off, const int64_t *seg_off,
@@ -333,9 +334,10 @@ __global__ void __launch_bounds__(kScanThreads) k_plan_seg_chunks(fptc_batch b, 
     const int c = sw.cnt[j];
     for (; mb < p + c && m < nc; ++m, mb += cb) {
       const int64_t w = sw.first + j;
-      meta[c0 + m].first_word = w;
-      meta[c0 + m].first_sym = (int32_t)(p - mb);
-      if (m > 0) meta[c0 + m - 1].word_end = p == mb ? w : w + 1;
+      // first word, first symbol and the last flag: one 16-byte store (the
+      // chunk before ends at this word, which its reader derives from these)
+      *reinterpret_cast<uint4 *>(meta + c0 + m) =
+          make_uint4((uint32_t)w, (uint32_t)((uint64_t)w >> 32), (uint32_t)(int32_t)(p - mb), m == nc - 1 ? 1u : 0u);
     }
     p += c;
   }
