@@ -107,6 +107,16 @@ __device__ inline void build_lut3(uint32_t *lut3, uint8_t *cl, uint32_t *info, c
           nf = 1;
         }
         while (c < 15) {
+          // a run of fill codes is a run of lf-bit zero groups: take it whole
+          // (leading zeros of the peek's remaining real bits), then one lookup
+          // for the code after it
+          const uint32_t v = (idx << len) & mask, real = (uint32_t)lmax - len;
+          uint32_t zr = v ? (uint32_t)__clz(v) - (32u - (uint32_t)lmax) : (uint32_t)lmax;
+          zr = zr < real ? zr : real;
+          const uint32_t k = min(zr / lf, 15u - c);
+          c += k;
+          len += k * lf;
+          if (c >= 15) break;
           const uint32_t e = L[(idx << len) & mask];
           const uint32_t l = e >> 8, s = e & 255u;
           if (l == 0 || len + l > (uint32_t)lmax) break;
