@@ -43,13 +43,14 @@ __host__ __device__ inline size_t fused_table_bytes(int bpieces, int n_books, in
          (bpieces <= 2 ? align16((size_t)n_books * n_rows * 256 * 4) : 0);
 }
 
-// LDS: lookup tables | split basis | dequantization tables | wave buffers.
-// The multi-symbol build borrows lut1_temp_bytes right after the tables.
+// LDS: lookup tables | split basis | dequantization tables | wave buffers |
+// chunk counter (16 B).  The multi-symbol build borrows lut1_temp_bytes right
+// after the tables.
 __host__ __device__ inline size_t fused_lds_bytes(bool ms, int bpieces, int N, int E, int Kp, int wpc, int waves,
                                                   int n_books, int n_rows, int lmax) {
   const size_t t = lut_lds_bytes(ms, n_books, lmax);
   const size_t need = t + (size_t)bpieces * N * (Kp + 8) * 2 + fused_table_bytes(bpieces, n_books, n_rows, E) +
-                      (size_t)waves * fused_wave_bytes(E, wpc);
+                      (size_t)waves * fused_wave_bytes(E, wpc) + 16;
   const size_t tmp = ms ? t + lut1_temp_bytes(n_books, lmax) : 0;
   return need > tmp ? need : tmp;
 }
@@ -95,6 +96,8 @@ __global__ void __launch_bounds__(64 * max_fused_waves(NT * 32)) k_fused(const u
     Rb[i] = (uint8_t)(r < n_rows ? r : n_rows - 1);
   }
   if constexpr (AP <= 2) stage_pieces<PREC>(Pq, deq_val, n_books * n_rows * 256, threadIdx.x, nthreads);
+  unsigned *chunk_ctr = reinterpret_cast<unsigned *>(wave_base + (size_t)waves * fused_wave_bytes(E, wpc));
+  if (threadIdx.x == 0) *chunk_ctr = 0;
   __syncthreads();
 
   const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -107,26 +110,29 @@ __global__ void __launch_bounds__(64 * max_fused_waves(NT * 32)) k_fused(const u
   const int64_t n_chunks = hdr[0];
   const int64_t cstride = (int64_t)gridDim.x * waves;
 
-  // Software pipeline over this wave's chunks c, c + cstride, ...: the words
-  // of chunk i+1 (and the record of chunk i+2) are requested before chunk i
-  // decodes and are waited for right after that decode, before chunk i's
-  // stores.  Vector memory counters retire in order, so this one wait also
-  // covers chunk i-1's stores, which had the whole decode to drain.
-  int64_t c = (int64_t)blockIdx.x * waves + wid;
+  // Software pipeline over this wave's chunks (taken from the workgroup's
+  // schedule): the words of chunk i+1 (and the record of chunk i+2) are
+  // requested before chunk i decodes and are waited for right after that
+  // decode, before chunk i's stores.  Vector memory counters retire in order,
+  // so this one wait also covers chunk i-1's stores, which had the whole
+  // decode to drain.
+  const BlockChunks sched{chunk_ctr, (int64_t)blockIdx.x * waves, cstride, waves};
+  int64_t c = sched.next(lane), cn = sched.next(lane);
   ChunkMeta cm = meta_from_lanes(load_meta_lane(meta, c, n_chunks, lane), c < n_chunks);
-  const uint32_t vn = load_meta_lane(meta, c + cstride, n_chunks, lane);
+  const uint32_t vn = load_meta_lane(meta, cn, n_chunks, lane);
   ChunkWords cw{};
   if (c < n_chunks) load_chunk_words(words, symlen, cm.first_word, cm.word_end, lane, cw);
-  ChunkMeta nm = meta_from_lanes(vn, c + cstride < n_chunks);
-  for (; c < n_chunks; c += cstride) {
+  ChunkMeta nm = meta_from_lanes(vn, cn < n_chunks);
+  while (c < n_chunks) {
+    const int64_t cmm = sched.next(lane);
     const bool ok = cm.first_word >= 0;  // else the stream's symbol count is wrong; already flagged
     const int s = cm.stream < 0 ? 0 : (cm.stream >= n_streams ? n_streams - 1 : cm.stream);
     const int book = cm.book < n_books && cm.book >= 0 ? cm.book : 0;
     const int w_cnt = cm.n_windows;
     const float vg = load_gamma_lane(gamma, s, lane);
-    const uint32_t vm = load_meta_lane(meta, c + 2 * cstride, n_chunks, lane);
+    const uint32_t vm = load_meta_lane(meta, cmm, n_chunks, lane);
     ChunkWords nx{};
-    if (c + cstride < n_chunks) load_chunk_words(words, symlen, nm.first_word, nm.word_end, lane, nx);
+    if (cn < n_chunks) load_chunk_words(words, symlen, nm.first_word, nm.word_end, lane, nx);
 
     // ---- 1. decode the chunk's symbols into sb[0 .. w_cnt * E)
     int err = 0;
@@ -139,7 +145,7 @@ __global__ void __launch_bounds__(64 * max_fused_waves(NT * 32)) k_fused(const u
     settle_chunk_words(nx);
     settle_lane(vm);
     settle_lane(vg);
-    const ChunkMeta mm = meta_from_lanes(vm, c + 2 * cstride < n_chunks);
+    const ChunkMeta mm = meta_from_lanes(vm, cmm < n_chunks);
     cw = nx;
     if (ok) {
       if (err && status) atomicOr(&status[s], err);
@@ -174,6 +180,8 @@ __global__ void __launch_bounds__(64 * max_fused_waves(NT * 32)) k_fused(const u
     }
     cm = nm;
     nm = mm;
+    c = cn;
+    cn = cmm;
   }
 }
 
