@@ -27,11 +27,12 @@ __host__ __device__ inline size_t decode_wave_bytes(int wpc, int E) {
   return (size_t)kSymPrefix + ((((size_t)wpc * E + 32) + 15) & ~(size_t)15);
 }
 
-// LDS: lookup tables, then one symbol buffer per wave; the multi-symbol
-// build borrows lut1_temp_bytes after the tables before the buffers are used.
+// LDS: lookup tables, then one symbol buffer per wave, then the chunk
+// counter (16 B); the multi-symbol build borrows lut1_temp_bytes after the
+// tables before the buffers are used.
 __host__ __device__ inline size_t decode_lds(bool ms, int n_books, int lmax, int wpc, int E, int waves) {
   const size_t t = lut_lds_bytes(ms, n_books, lmax);
-  const size_t need = t + (size_t)waves * decode_wave_bytes(wpc, E);
+  const size_t need = t + (size_t)waves * decode_wave_bytes(wpc, E) + 16;
   const size_t tmp = ms ? t + lut1_temp_bytes(n_books, lmax) : 0;
   return need > tmp ? need : tmp;
 }
@@ -56,6 +57,10 @@ __global__ void __launch_bounds__(1024) k_decode(const uint64_t *__restrict__ wo
   const int64_t n_chunks = hdr[0];
   const int waves_per_block = blockDim.x / kWave;
   const int64_t cstride = (int64_t)gridDim.x * waves_per_block;
+  // the counter may share LDS with the table build's scratch: set after it
+  unsigned *chunk_ctr = reinterpret_cast<unsigned *>(lds + lut_bytes + waves_per_block * decode_wave_bytes(wpc, E));
+  if (threadIdx.x == 0) *chunk_ctr = 0;
+  __syncthreads();
   const int hs = 32 - lmax;
 
   // Software pipeline over this wave's chunks: the words of the next chunk
@@ -63,16 +68,19 @@ __global__ void __launch_bounds__(1024) k_decode(const uint64_t *__restrict__ wo
   // decodes and waited for right after the decode, before this chunk's
   // stores; with in-order vector memory counters that wait also covers the
   // previous chunk's stores, which had the decode to drain.
-  int64_t c = (int64_t)blockIdx.x * waves_per_block + wid;
+  // (chunks from the workgroup's schedule, BlockChunks)
+  const BlockChunks sched{chunk_ctr, (int64_t)blockIdx.x * waves_per_block, cstride, waves_per_block};
+  int64_t c = sched.next(lane), cn = sched.next(lane);
   ChunkMeta cm = meta_from_lanes(load_meta_lane(meta, c, n_chunks, lane), c < n_chunks);
-  const uint32_t vn = load_meta_lane(meta, c + cstride, n_chunks, lane);
+  const uint32_t vn = load_meta_lane(meta, cn, n_chunks, lane);
   ChunkWords cw{};
   if (c < n_chunks) load_chunk_words(words, symlen, cm.first_word, cm.word_end, lane, cw);
-  ChunkMeta nm = meta_from_lanes(vn, c + cstride < n_chunks);
-  for (; c < n_chunks; c += cstride) {
-    const uint32_t vm = load_meta_lane(meta, c + 2 * cstride, n_chunks, lane);
+  ChunkMeta nm = meta_from_lanes(vn, cn < n_chunks);
+  while (c < n_chunks) {
+    const int64_t cmm = sched.next(lane);
+    const uint32_t vm = load_meta_lane(meta, cmm, n_chunks, lane);
     ChunkWords nx{};
-    if (c + cstride < n_chunks) load_chunk_words(words, symlen, nm.first_word, nm.word_end, lane, nx);
+    if (cn < n_chunks) load_chunk_words(words, symlen, nm.first_word, nm.word_end, lane, nx);
     const bool ok = cm.first_word >= 0;  // else the stream's symbol count is wrong; already flagged
     const int s = cm.stream < 0 ? 0 : (cm.stream >= n_streams ? n_streams - 1 : cm.stream);
     const int book = cm.book < n_books && cm.book >= 0 ? cm.book : 0;
@@ -88,7 +96,7 @@ __global__ void __launch_bounds__(1024) k_decode(const uint64_t *__restrict__ wo
     }
     settle_chunk_words(nx);
     settle_lane(vm);
-    const ChunkMeta mm = meta_from_lanes(vm, c + 2 * cstride < n_chunks);
+    const ChunkMeta mm = meta_from_lanes(vm, cmm < n_chunks);
     cw = nx;
     if (ok) {
       if (err && status) atomicOr(&status[s], err);
@@ -114,6 +122,8 @@ __global__ void __launch_bounds__(1024) k_decode(const uint64_t *__restrict__ wo
     }
     cm = nm;
     nm = mm;
+    c = cn;
+    cn = cmm;
   }
 }
 

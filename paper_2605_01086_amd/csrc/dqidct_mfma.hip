@@ -41,10 +41,10 @@ __host__ __device__ constexpr size_t table_bytes(int bpieces, int n_books, int n
 }
 
 // LDS bytes of one instantiation: basis pieces, tables, one 32-window symbol
-// tile per wave.
+// tile per wave, the chunk counter (16 B).
 __host__ __device__ constexpr size_t mfma_lds_bytes(int bpieces, int N, int Kp, int n_books, int n_rows, int E) {
   return (size_t)bpieces * N * (Kp + 8) * 2 + table_bytes(bpieces, n_books, n_rows, E) +
-         (size_t)kWaves * (16 + a16((size_t)kTileWindows * E + 16));
+         (size_t)kWaves * (16 + a16((size_t)kTileWindows * E + 16)) + 16;
 }
 
 // The symbols of a 32-window tile, 16 bytes per lane per round: R rounds of
@@ -134,6 +134,8 @@ __global__ void __launch_bounds__(kThreads, NT >= 4 ? 2 : (NT == 2 ? 3 : 4)) k_d
     Rb[i] = (uint8_t)(r < n_rows ? r : n_rows - 1);
   }
   if constexpr (AP <= 2) stage_pieces<PREC>(Pq, deq_val, n_books * n_rows * 256, threadIdx.x, kThreads);
+  unsigned *chunk_ctr = reinterpret_cast<unsigned *>(bufs + (size_t)kWaves * (16 + a16((size_t)kTileWindows * E + 16)));
+  if (threadIdx.x == 0) *chunk_ctr = 0;
   __syncthreads();
 
   const int lane = threadIdx.x & 63, col = lane & 31, h = lane >> 5;
@@ -144,27 +146,30 @@ __global__ void __launch_bounds__(kThreads, NT >= 4 ? 2 : (NT == 2 ? 3 : 4)) k_d
   const float oscale = 1.0f / bscale;
   const bool vec16 = (E % 16) == 0 && (reinterpret_cast<uintptr_t>(symbols) & 15) == 0;
 
-  int64_t c = (int64_t)blockIdx.x * kWaves + wid;
+  // chunks from the workgroup's schedule (BlockChunks)
+  const BlockChunks sched{chunk_ctr, (int64_t)blockIdx.x * kWaves, cstride, kWaves};
+  int64_t c = sched.next(lane), cn = sched.next(lane);
   ChunkMeta cm = meta_from_lanes(load_meta_lane(meta, c, n_chunks, lane), c < n_chunks);
-  const uint32_t vn = load_meta_lane(meta, c + cstride, n_chunks, lane);
+  const uint32_t vn = load_meta_lane(meta, cn, n_chunks, lane);
   TileSyms<NT> cur{};
   if (c < n_chunks)
     load_tile_syms(symbols, b.n_symbols, cm.sym_base, min(kTileWindows, cm.n_windows) * E, vec16, lane, cur);
-  ChunkMeta nm = meta_from_lanes(vn, c + cstride < n_chunks);
+  ChunkMeta nm = meta_from_lanes(vn, cn < n_chunks);
   auto stream_of = [&](const ChunkMeta &m) {
     return m.stream < 0 ? 0 : (m.stream >= b.n_streams ? b.n_streams - 1 : m.stream);
   };
   // per-stream scales of the current chunk, requested one chunk ahead
   float vg = load_gamma_lane(gamma, stream_of(cm), lane);
   settle_lane(vg);
-  for (; c < n_chunks; c += cstride) {
+  while (c < n_chunks) {
     const int book = cm.book < n_books && cm.book >= 0 ? cm.book : 0;
     const int w_cnt = cm.n_windows;
     const float g0 = lane_float(vg, 0), g1 = lane_float(vg, 1), g2 = lane_float(vg, 2);
-    const uint32_t vm = load_meta_lane(meta, c + 2 * cstride, n_chunks, lane);
+    const int64_t cmm = sched.next(lane);
+    const uint32_t vm = load_meta_lane(meta, cmm, n_chunks, lane);
     const float vgn = load_gamma_lane(gamma, stream_of(nm), lane);
     TileSyms<NT> nx{};
-    if (c + cstride < n_chunks)
+    if (cn < n_chunks)
       load_tile_syms(symbols, b.n_symbols, nm.sym_base, min(kTileWindows, nm.n_windows) * E, vec16, lane, nx);
     for (int tt = 0; tt * kTileWindows < w_cnt; ++tt) {
       const int wt = min(kTileWindows, w_cnt - tt * kTileWindows);
@@ -207,7 +212,9 @@ __global__ void __launch_bounds__(kThreads, NT >= 4 ? 2 : (NT == 2 ? 3 : 4)) k_d
     settle_lane(vgn);
     cur = nx;
     cm = nm;
-    nm = meta_from_lanes(vm, c + 2 * cstride < n_chunks);
+    nm = meta_from_lanes(vm, cmm < n_chunks);
+    c = cn;
+    cn = cmm;
     vg = vgn;
   }
 }
