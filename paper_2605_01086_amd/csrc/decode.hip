@@ -69,7 +69,7 @@ __global__ void __launch_bounds__(1024) k_decode(const uint64_t *__restrict__ wo
   // stores; with in-order vector memory counters that wait also covers the
   // previous chunk's stores, which had the decode to drain.
   // (chunks from the workgroup's schedule, BlockChunks)
-  const BlockChunks sched{chunk_ctr, (int64_t)blockIdx.x * waves_per_block, cstride, waves_per_block};
+  const BlockChunks sched{chunk_ctr, (int64_t)blockIdx.x, cstride, (int64_t)gridDim.x, waves_per_block};
   int64_t c = sched.next(lane), cn = sched.next(lane);
   ChunkMeta cm = meta_from_lanes(load_meta_lane(meta, c, n_chunks, lane), c < n_chunks);
   const uint32_t vn = load_meta_lane(meta, cn, n_chunks, lane);

@@ -147,7 +147,7 @@ __global__ void __launch_bounds__(kThreads, NT >= 4 ? 2 : (NT == 2 ? 3 : 4)) k_d
   const bool vec16 = (E % 16) == 0 && (reinterpret_cast<uintptr_t>(symbols) & 15) == 0;
 
   // chunks from the workgroup's schedule (BlockChunks)
-  const BlockChunks sched{chunk_ctr, (int64_t)blockIdx.x * kWaves, cstride, kWaves};
+  const BlockChunks sched{chunk_ctr, (int64_t)blockIdx.x * kWaves, cstride, 1, kWaves};
   int64_t c = sched.next(lane), cn = sched.next(lane);
   ChunkMeta cm = meta_from_lanes(load_meta_lane(meta, c, n_chunks, lane), c < n_chunks);
   const uint32_t vn = load_meta_lane(meta, cn, n_chunks, lane);

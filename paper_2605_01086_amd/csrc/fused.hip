@@ -116,7 +116,7 @@ __global__ void __launch_bounds__(64 * max_fused_waves(NT * 32)) k_fused(const u
   // decode, before chunk i's stores.  Vector memory counters retire in order,
   // so this one wait also covers chunk i-1's stores, which had the whole
   // decode to drain.
-  const BlockChunks sched{chunk_ctr, (int64_t)blockIdx.x * waves, cstride, waves};
+  const BlockChunks sched{chunk_ctr, (int64_t)blockIdx.x * waves, cstride, 1, waves};
   int64_t c = sched.next(lane), cn = sched.next(lane);
   ChunkMeta cm = meta_from_lanes(load_meta_lane(meta, c, n_chunks, lane), c < n_chunks);
   const uint32_t vn = load_meta_lane(meta, cn, n_chunks, lane);

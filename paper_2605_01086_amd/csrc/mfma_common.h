@@ -455,22 +455,25 @@ __device__ inline ChunkMeta meta_from_lanes(uint32_t d, bool valid) {
   }
   return m;
 }
-// Chunk schedule of a persistent workgroup: its chunks are base + j + k stride
-// (j < waves, k = 0, 1, ...), in increasing order, handed out one at a time
-// through a counter in LDS.  A SIMD's arbiter favours its older waves, so
-// with a fixed share per wave the younger ones fall behind and finish last
-// while the older ones leave their SIMDs half empty; with the shared counter
-// a wave takes the next chunk whenever it is ready.  Indices only grow, so a
-// wave stops at the first one past the end.
+// Chunk schedule of a persistent workgroup: in each round of `stride` chunks
+// (workgroups x waves) it takes base + j step (j < waves), in increasing
+// order, handed out one at a time through a counter in LDS.  step 1 keeps a
+// round's chunks of one workgroup adjacent (neighbouring output and input);
+// step = the number of workgroups draws them from many streams, so that the
+// rounds' costs even out across workgroups.  A SIMD's arbiter favours its older
+// waves, so with a fixed share per wave the younger ones fall behind and
+// finish last while the older ones leave their SIMDs half empty; with the
+// shared counter a wave takes the next chunk whenever it is ready.  Indices
+// only grow, so a wave stops at the first one past the end.
 struct BlockChunks {
   unsigned *ctr;  // LDS, zeroed before the loop
-  int64_t base, stride;
+  int64_t base, stride, step;
   int waves;
   __device__ int64_t next(int lane) const {
     unsigned t = 0;
     if (lane == 0) t = atomicAdd(ctr, 1u);
     t = __builtin_amdgcn_readfirstlane(t);
-    return base + (int64_t)(t % (unsigned)waves) + (int64_t)(t / (unsigned)waves) * stride;
+    return base + (int64_t)(t % (unsigned)waves) * step + (int64_t)(t / (unsigned)waves) * stride;
   }
 };
 
