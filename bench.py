@@ -285,7 +285,9 @@ def main():
     ap.add_argument("--wpc", type=int, default=32)
     ap.add_argument("--waves", type=int, default=0, help="waves per block (0 = library default)")
     ap.add_argument("--autotune", action="store_true", help="pick the launch shape by timing candidates")
-    ap.add_argument("--graph", action="store_true", help="replay the step as one captured HIP graph")
+    ap.add_argument("--graph", dest="graph", action="store_true", default=True,
+                    help="time the step as replays of one captured HIP graph (plan + decode kernels; default)")
+    ap.add_argument("--no-graph", dest="graph", action="store_false", help="time eager launches instead")
     ap.add_argument("--blocks", type=int, default=0)
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -332,6 +334,7 @@ def main():
         launch, tuned = autotune.tune(batch, codec, args.precision, fused, use_cache=False)
     dec = C.Decoder(batch, codec, launch)
     ms_step, per_kernel, gpu_steps = time_batched(dec, args.steps, args.warmup, args.precision, fused)
+    eager_ms = ms_step
     graph_ms = None
     if args.graph:
         from paper_2605_01086_amd.graph import CapturedStep
@@ -396,6 +399,7 @@ def main():
                           "roofline_decoded_GBs": round(path_roofline_decoded, 1),
                           "decoded_frac_of_roofline": round(value / path_roofline_decoded, 4)},
         "stage_ms": {k: round(float(v), 4) for k, v in zip(names, stage_ms)},
+        "eager_ms_per_step": round(float(eager_ms), 4),
         "autotune_ms": tuned,
         "gpu_ms_per_step": {"median": round(float(np.median(gpu_steps)), 4), "min": round(float(gpu_steps.min()), 4),
                             "max": round(float(gpu_steps.max()), 4)},
