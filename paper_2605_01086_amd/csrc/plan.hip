@@ -58,6 +58,7 @@ __device__ inline T block_excl_scan(T v, T *lds, T &total) {
 // streams (all their offsets loaded at once), so a batch of up to
 // kPlanThreads * kStreamsPerThread streams needs one pass of block scans.
 constexpr int kStreamsPerThread = 4;
+
 __global__ void __launch_bounds__(kPlanThreads) k_plan_streams(fptc_batch b, int N, int E, int wpc,
                                                                int64_t *hdr, int64_t *win_off, int64_t *chunk_off,
                                                                int64_t *seg_off, int32_t *seg_stream,
@@ -186,11 +187,34 @@ struct SegWords {
   int cnt[kWordsPerThread];
 };
 
-__device__ inline int load_seg_words(const fptc_batch &b, int64_t g, const int64_t *seg_off,
-                                     const int32_t *seg_stream, int s, SegWords &sw) {
-  const int64_t w0 = b.word_off[s], w1 = b.word_off[s + 1];
+__device__ inline int clamp_stream(int s, int n) { return s < 0 ? 0 : (s >= n ? n - 1 : s); }
+
+// An empty asm statement that reads a uniform value: the compiler must have
+// loaded it here, so loads pinned this way are issued together and waited
+// for once, instead of one round trip each as their uses come.
+__device__ inline void pin(int64_t x) { asm volatile("" ::"s"(x)); }
+
+// The segment's stream and its word range, loaded together with everything
+// else the kernel needs of the stream, before any check waits on them.
+struct SegStream {
+  int s;
+  int64_t w0, w1, g0, g1;  // the stream's words, its segments
+};
+
+__device__ inline SegStream seg_stream_of(const fptc_batch &b, int s, const int64_t *seg_off) {
+  SegStream t;
+  t.s = s;
+  t.w0 = b.word_off[s];
+  t.w1 = b.word_off[s + 1];
+  t.g0 = seg_off[s];
+  t.g1 = seg_off[s + 1];
+  return t;
+}
+
+__device__ inline int load_seg_words(const fptc_batch &b, int64_t g, const SegStream &t, SegWords &sw) {
+  const int64_t w0 = t.w0, w1 = t.w1;
   const int64_t a0 = w0 & ~(int64_t)15;
-  const int64_t first = a0 + (g - seg_off[s]) * kSegWords + (int64_t)threadIdx.x * kWordsPerThread;
+  const int64_t first = a0 + (g - t.g0) * kSegWords + (int64_t)threadIdx.x * kWordsPerThread;
   sw.first = first;
   uint8_t c[kWordsPerThread];
   if ((reinterpret_cast<uintptr_t>(b.symlen) & 15) == 0 && first >= w0 && first + kWordsPerThread <= w1) {
@@ -224,12 +248,18 @@ __global__ void __launch_bounds__(kScanThreads) k_plan_seg_sums(fptc_batch b, co
                                                                 const int64_t *seg_off, const int32_t *seg_stream,
                                                                 int32_t *seg_sum, int32_t *status) {
   __shared__ int lds[kScanThreads / kWave];
+  if (b.n_streams <= 0) return;
   const int64_t g = blockIdx.x;
-  const int s = seg_stream[g];  // read with the header (in bounds; used once g is known to be valid)
-  if (g >= hdr[2]) return;
-  if (seg_off[s + 1] > hdr[3]) return;  // the stream's segments did not fit (flagged)
+  // g < seg_cap, so this read is in bounds; past the plan's segments it may
+  // hold anything, so it is clamped to a stream before the stream's offsets
+  // are read with it (such a block then returns on the header check)
+  const int s = clamp_stream(seg_stream[g], b.n_streams);
+  const int64_t h2 = hdr[2], seg_cap = hdr[3];
+  const SegStream t = seg_stream_of(b, s, seg_off);
+  pin(t.w0), pin(t.w1), pin(t.g0), pin(t.g1), pin(h2), pin(seg_cap);
+  if (g >= h2 || t.g1 > seg_cap) return;  // past the plan, or the stream's segments did not fit (flagged)
   SegWords sw;
-  const int bad = load_seg_words(b, g, seg_off, seg_stream, s, sw);
+  const int bad = load_seg_words(b, g, t, sw);
   int sum = 0;
 #pragma unroll
   for (int j = 0; j < kWordsPerThread; ++j) sum += sw.cnt[j];
@@ -311,19 +341,24 @@ __global__ void __launch_bounds__(kScanThreads) k_plan_seg_chunks(fptc_batch b, 
                                                                   const int32_t *seg_stream,
                                                                   const int64_t *seg_base, ChunkMeta *meta) {
   __shared__ int lds[kScanThreads / kWave];
+  if (b.n_streams <= 0) return;
   const int64_t g = blockIdx.x;
-  const int s = seg_stream[g];  // read with the header (in bounds; used once g is known to be valid)
+  // as in k_plan_seg_sums: the stream index is clamped before any read with it
+  const int s = clamp_stream(seg_stream[g], b.n_streams);
   const int64_t gb = seg_base[g];
-  if (g >= hdr[2]) return;
-  if (seg_off[s + 1] > hdr[3]) return;  // the stream's segments did not fit (flagged)
+  const int64_t h2 = hdr[2], seg_cap = hdr[3];
+  // everything of the stream at once: one round trip before the words
+  const SegStream t = seg_stream_of(b, s, seg_off);
+  const int64_t c0 = chunk_off[s], nc = chunk_off[s + 1] - c0;
+  pin(t.w0), pin(t.w1), pin(t.g0), pin(t.g1), pin(h2), pin(seg_cap), pin(gb), pin(c0), pin(nc);
+  if (g >= h2 || t.g1 > seg_cap) return;  // past the plan, or the stream's segments did not fit (flagged)
   SegWords sw;
-  load_seg_words(b, g, seg_off, seg_stream, s, sw);
+  load_seg_words(b, g, t, sw);
   int sum = 0;
 #pragma unroll
   for (int j = 0; j < kWordsPerThread; ++j) sum += sw.cnt[j];
   int tot;
   const int ex = block_excl_scan_dpp(sum, lds, tot);
-  const int64_t c0 = chunk_off[s], nc = chunk_off[s + 1] - c0;
   const int64_t cb = (int64_t)wpc * E;  // symbols per chunk
   int64_t p = gb + ex;
   // the boundaries inside this thread's words, from the first at or after p

@@ -136,3 +136,67 @@ def test_overrun_flags_match_the_oracle(fused):
     for s in range(len(lens)):
         assert bool(st[s] & F.FPTC_STREAM_OVERRUN) == expect[s], (s, int(st[s]), expect[s])
         assert (int(st[s]) & ~F.FPTC_STREAM_OVERRUN) == 0, (s, int(st[s]))
+
+
+@pytest.mark.parametrize("fused", [False, True])
+def test_short_stream_skips_the_chunks_no_word_reaches(fused):
+    # Stream 1's second half of words claims no symbols, so the chunks whose
+    # first symbol lies past what its words hold have no first word: they are
+    # skipped (their symbols and samples stay untouched) and the stream is
+    # flagged.  The workspace first holds valid records of the intact batch,
+    # so a record the plan failed to rewrite would decode that batch's chunk.
+    import torch
+    from paper_2605_01086_amd import codec as C
+    from paper_2605_01086_amd import fptc as F
+    from gpu_helpers import PAD, SENT_F32, SENT_U8, qparams
+    lens = [9000, 12000, 7000]
+    c = build_case(_amp(64), ["eeg", "seismic"], lens, config_id=740)
+    words, symlen, word_off, sample_off = c.concat()
+    sl = symlen.copy()
+    a, b = int(word_off[1]), int(word_off[2])
+    sl[(a + b) // 2:b] = 0
+    codec = C.DeviceCodec(np.stack([bk.lengths for bk in c.books]), qparams(c.p), 12)
+    good = C.DeviceBatch(words, symlen, word_off, sample_off, c.p.N, c.p.E, c.book_id)
+    bad = C.DeviceBatch(words, sl, word_off, sample_off, c.p.N, c.p.E, c.book_id)
+    lc = C.Launch().c()
+    dev = good.word_off.device
+    ws = torch.empty(F.fptc_workspace_size(good.c, codec.c, lc), dtype=torch.uint8, device=dev)
+    status = torch.zeros((good.n_streams,), dtype=torch.int32, device=dev)
+    sym = torch.empty((good.n_symbols + PAD,), dtype=torch.uint8, device=dev)
+    out = torch.empty((good.n_samples + PAD,), dtype=torch.float32, device=dev)
+
+    def run(batch):
+        sym.fill_(SENT_U8)
+        out.fill_(float(SENT_F32))
+        F.fptc_plan_batch(batch.c, codec.c, lc, ws, status)
+        if fused:
+            F.fptc_decompress_batch(batch.c, codec.c, lc, ws, None, "fp16x2", out, status)
+        else:
+            F.fptc_decode_batch(batch.c, codec.c, lc, ws, sym, status)
+        torch.cuda.synchronize()
+        return sym.cpu().numpy().copy(), out.cpu().numpy().copy(), status.cpu().numpy().copy()
+
+    run(good)
+    s_h, o_h, st = run(bad)
+    assert st[1] & F.FPTC_STREAM_BAD_COUNT, int(st[1])
+    assert st[0] == 0 and st[2] == 0, st
+    wpc = C.Launch().windows_per_chunk
+    cb = wpc * c.p.E  # symbols per chunk
+    carry = int(np.minimum(sl[a:b], 64).astype(np.int64).sum())
+    reached = -(-carry // cb)
+    n_win = -(-lens[1] // c.p.N)
+    n_chunks = -(-n_win // wpc)
+    assert 0 < reached < n_chunks, (reached, n_chunks)
+    if fused:
+        o0 = int(bad.sample_off_h[1]) + reached * wpc * c.p.N
+        assert np.all(o_h[o0:int(bad.sample_off_h[2])] == SENT_F32)
+    else:
+        y0 = int(bad.sym_off_h[1]) + reached * cb
+        assert np.all(s_h[y0:int(bad.sym_off_h[2])] == SENT_U8)
+    res = dict(sym=s_h[:bad.n_symbols], out=o_h[:bad.n_samples], status=st, batch=bad)
+    if fused:
+        check_parity(c, res, skip={1}, check_symbols=False, tol=1e-5)
+    else:
+        for i in (0, 2):
+            y0, y1 = bad.sym_off_h[i], bad.sym_off_h[i + 1]
+            assert np.array_equal(res["sym"][y0:y1], c.symbols[i]), i
