@@ -15,8 +15,14 @@ namespace {
 
 constexpr int kPlanThreads = 1024;
 constexpr int kScanThreads = 256;
-constexpr int kWordsPerThread = 16;  // one 16-byte symlen load per thread
-constexpr int64_t kSegWords = (int64_t)kScanThreads * kWordsPerThread;  // words per segment
+constexpr int64_t kSegWords = 4096;  // words per segment
+// The segment sums take a segment per wavefront (64 lanes x 64 words, four
+// 16-byte symlen loads per lane): one-wave workgroups need no barrier in
+// their scan, and more of them fit on a CU at once, which is what a
+// latency-bound pass over many small segments needs.  The chunk-start pass
+// walks every word's symbol range, so it keeps 256 threads x 16 words.
+constexpr int kSumThreads = kWave;
+constexpr int kChunkThreads = 256;
 
 // Inclusive scan across one 64-lane wavefront.
 template <typename T>
@@ -160,31 +166,14 @@ __global__ void __launch_bounds__(kPlanThreads) k_plan_streams(fptc_batch b, int
   }
 }
 
-// Exclusive block scan of int values with DPP wave scans; returns the
-// exclusive prefix and the block total.
-__device__ inline int block_excl_scan_dpp(int v, int *lds, int &total) {
-  const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
-  constexpr int NW = kScanThreads / kWave;
-  const int incl = wave_incl_scan_dpp(v);
-  if (lane == kWave - 1) lds[wid] = incl;
-  __syncthreads();
-  int before = 0, tot = 0;
-#pragma unroll
-  for (int i = 0; i < NW; ++i) {
-    const int x = lds[i];
-    before += i < wid ? x : 0;
-    tot += x;
-  }
-  __syncthreads();
-  total = tot;
-  return before + incl - v;
-}
-
-// The words of one segment: this thread's 16 symlen bytes (words outside the
-// stream read as 0), each clamped to 64 with the clamp reported.
+// The words of one segment: this thread's WPT symlen bytes, packed four to a
+// dword (words outside the stream read as 0), each clamped to 64 with the
+// clamp reported.
+template <int WPT>
 struct SegWords {
-  int64_t first;  // global index of this thread's first word
-  int cnt[kWordsPerThread];
+  int64_t first;  // global index of this lane's first word
+  uint32_t x[WPT / 4];
+  __device__ int cnt(int j) const { return (int)((x[j >> 2] >> (8 * (j & 3))) & 255u); }
 };
 
 __device__ inline int clamp_stream(int s, int n) { return s < 0 ? 0 : (s >= n ? n - 1 : s); }
@@ -211,43 +200,104 @@ __device__ inline SegStream seg_stream_of(const fptc_batch &b, int s, const int6
   return t;
 }
 
-__device__ inline int load_seg_words(const fptc_batch &b, int64_t g, const SegStream &t, SegWords &sw) {
-  const int64_t w0 = t.w0, w1 = t.w1;
-  const int64_t a0 = w0 & ~(int64_t)15;
-  const int64_t first = a0 + (g - t.g0) * kSegWords + (int64_t)threadIdx.x * kWordsPerThread;
+template <int WPT>
+__device__ inline int load_seg_words(const fptc_batch &b, int64_t g, const SegStream &t, SegWords<WPT> &sw) {
+  static_assert(WPT % 16 == 0, "whole 16-byte symlen blocks per thread");
+  const int64_t a0 = t.w0 & ~(int64_t)15;
+  const int64_t first = a0 + (g - t.g0) * kSegWords + (int64_t)threadIdx.x * WPT;
   sw.first = first;
-  uint8_t c[kWordsPerThread];
-  if ((reinterpret_cast<uintptr_t>(b.symlen) & 15) == 0 && first >= w0 && first + kWordsPerThread <= w1) {
-    const uint4 u = *reinterpret_cast<const uint4 *>(b.symlen + first);
-    const uint32_t x[4] = {u.x, u.y, u.z, u.w};
+  const bool aligned = (reinterpret_cast<uintptr_t>(b.symlen) & 15) == 0;
 #pragma unroll
-    for (int j = 0; j < kWordsPerThread; ++j) c[j] = (uint8_t)(x[j >> 2] >> (8 * (j & 3)));
-  } else {
+  for (int q = 0; q < WPT / 16; ++q) {
+    const int64_t f = first + 16 * q;
+    uint32_t *x = sw.x + 4 * q;
+    x[0] = x[1] = x[2] = x[3] = 0;
+    if (f + 16 <= t.w0 || f >= t.w1) continue;  // no word of the stream
+    if (aligned && f + 16 <= b.n_words) {
+      // a whole 16-byte block inside the array (f is a multiple of 16);
+      // bytes outside the stream are cleared below
+      const uint4 u = *reinterpret_cast<const uint4 *>(b.symlen + f);
+      x[0] = u.x, x[1] = u.y, x[2] = u.z, x[3] = u.w;
+    } else {
 #pragma unroll
-    for (int j = 0; j < kWordsPerThread; ++j) {
-      const int64_t w = first + j;
-      c[j] = (w >= w0 && w < w1) ? b.symlen[w] : (uint8_t)0;
+      for (int j = 0; j < 16; ++j)
+        if (f + j >= t.w0 && f + j < t.w1) x[j >> 2] |= (uint32_t)b.symlen[f + j] << (8 * (j & 3));
     }
   }
+  // clear the bytes before the stream's first and from its last word on
+  // (only the lanes at the stream's two ends have any)
+  const int64_t lo64 = t.w0 - first, hi64 = t.w1 - first;
+  if (lo64 > 0 || hi64 < WPT) {
+    const int lo = lo64 > 0 ? (int)(lo64 < WPT ? lo64 : WPT) : 0;
+    const int hi = hi64 < WPT ? (int)(hi64 > 0 ? hi64 : 0) : WPT;
+#pragma unroll
+    for (int d = 0; d < WPT / 4; ++d) {
+      uint32_t m = 0;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) m |= (4 * d + k >= lo && 4 * d + k < hi) ? (255u << (8 * k)) : 0u;
+      sw.x[d] &= m;
+    }
+  }
+  // a count above 64 (a byte of 65 or more) is clamped and reported
   int bad = 0;
 #pragma unroll
-  for (int j = 0; j < kWordsPerThread; ++j) {
-    int v = c[j];
-    if (v > 64) {
+  for (int d = 0; d < WPT / 4; ++d) {
+    const uint32_t v = sw.x[d];
+    if ((v & 0x80808080u) | (((v & 0x7f7f7f7fu) + 0x3f3f3f3fu) & 0x80808080u)) {
+      uint32_t c = 0;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const uint32_t e = (v >> (8 * k)) & 255u;
+        c |= (e > 64u ? 64u : e) << (8 * k);
+      }
+      sw.x[d] = c;
       bad = FPTC_STREAM_BAD_SYMLEN;
-      v = 64;
     }
-    sw.cnt[j] = v;
   }
   return bad;
 }
 
+// The sum of a thread's counts.
+template <int WPT>
+__device__ inline int seg_words_sum(const SegWords<WPT> &sw) {
+  uint32_t sum = 0;
+#pragma unroll
+  for (int d = 0; d < WPT / 4; ++d) sum = __builtin_amdgcn_sad_u8(sw.x[d], 0u, sum);
+  return (int)sum;
+}
+
+// Exclusive block scan of int values (kChunkThreads threads) with DPP wave
+// scans; returns the exclusive prefix and the block total.
+__device__ inline int block_excl_scan_dpp(int v, int *lds, int &total) {
+  const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+  constexpr int NW = kChunkThreads / kWave;
+  const int incl = wave_incl_scan_dpp(v);
+  if (lane == kWave - 1) lds[wid] = incl;
+  __syncthreads();
+  int before = 0, tot = 0;
+#pragma unroll
+  for (int i = 0; i < NW; ++i) {
+    const int x = lds[i];
+    before += i < wid ? x : 0;
+    tot += x;
+  }
+  __syncthreads();
+  total = tot;
+  return before + incl - v;
+}
+
+// Exclusive scan across the segment's one wavefront; total = the wave's sum.
+__device__ inline int seg_excl_scan(int v, int &total) {
+  const int incl = wave_incl_scan_dpp(v);
+  total = __builtin_amdgcn_readlane(incl, kWave - 1);
+  return incl - v;
+}
+
 // One workgroup per segment: the segment's symbol count (symlen clamped to
 // 64; a larger symlen is flagged).
-__global__ void __launch_bounds__(kScanThreads) k_plan_seg_sums(fptc_batch b, const int64_t *hdr,
+__global__ void __launch_bounds__(kSumThreads) k_plan_seg_sums(fptc_batch b, const int64_t *hdr,
                                                                 const int64_t *seg_off, const int32_t *seg_stream,
                                                                 int32_t *seg_sum, int32_t *status) {
-  __shared__ int lds[kScanThreads / kWave];
   if (b.n_streams <= 0) return;
   const int64_t g = blockIdx.x;
   // g < seg_cap, so this read is in bounds; past the plan's segments it may
@@ -258,13 +308,10 @@ __global__ void __launch_bounds__(kScanThreads) k_plan_seg_sums(fptc_batch b, co
   const SegStream t = seg_stream_of(b, s, seg_off);
   pin(t.w0), pin(t.w1), pin(t.g0), pin(t.g1), pin(h2), pin(seg_cap);
   if (g >= h2 || t.g1 > seg_cap) return;  // past the plan, or the stream's segments did not fit (flagged)
-  SegWords sw;
+  SegWords<kSegWords / kSumThreads> sw;
   const int bad = load_seg_words(b, g, t, sw);
-  int sum = 0;
-#pragma unroll
-  for (int j = 0; j < kWordsPerThread; ++j) sum += sw.cnt[j];
   int tot;
-  block_excl_scan_dpp(sum, lds, tot);
+  seg_excl_scan(seg_words_sum(sw), tot);
   if (threadIdx.x == 0) seg_sum[g] = tot;
   if (bad && status) atomicOr(&status[s], bad);
 }
@@ -281,19 +328,23 @@ __global__ void __launch_bounds__(kScanThreads) k_plan_stream_scan(fptc_batch b,
                                                                    int32_t *status) {
   __shared__ int64_t lds[kScanThreads / kWave + 1];
   const int s = blockIdx.x;
+  // everything of the stream at once: one round trip before any use
+  const int64_t wo0 = win_off[s], wo1 = win_off[s + 1];
+  const int64_t c0 = chunk_off[s], nc = chunk_off[s + 1] - c0;
+  const int64_t w1 = b.word_off[s + 1];
+  const int64_t so = b.sample_off[s], L = b.sample_off[s + 1] - so;
+  const int64_t g0 = seg_off[s], g1 = seg_off[s + 1];
+  pin(wo0), pin(wo1), pin(c0), pin(nc), pin(w1), pin(so), pin(L), pin(g0), pin(g1);
   // Every stream, valid or not, records itself as the owner of the 32-window
   // tiles whose first window it holds, so a tile's first stream is one load.
   {
-    const int64_t t0 = (win_off[s] + kTileWindows - 1) / kTileWindows;
-    const int64_t t1 = (win_off[s + 1] + kTileWindows - 1) / kTileWindows;
+    const int64_t t0 = (wo0 + kTileWindows - 1) / kTileWindows;
+    const int64_t t1 = (wo1 + kTileWindows - 1) / kTileWindows;
     for (int64_t t = t0 + threadIdx.x; t < t1 && t < tile_cap; t += kScanThreads) tile_stream[t] = s;
   }
-  const int64_t c0 = chunk_off[s], nc = chunk_off[s + 1] - c0;
   if (nc <= 0) return;  // empty stream or bad header (then status already flagged)
-  const int64_t w1 = b.word_off[s + 1];
-  const int64_t nw = win_off[s + 1] - win_off[s];
+  const int64_t nw = wo1 - wo0;
   {
-    const int64_t so = b.sample_off[s], L = b.sample_off[s + 1] - so;
     const int bk = b.book_id ? (int)b.book_id[s] : 0;
     for (int64_t i = threadIdx.x; i < nc; i += kScanThreads) {
       ChunkMeta cm;
@@ -304,7 +355,7 @@ __global__ void __launch_bounds__(kScanThreads) k_plan_stream_scan(fptc_batch b,
       cm.first_sym = 0;
       cm.last = i == nc - 1;
       cm.word_end = w1;
-      cm.sym_base = win_off[s] * E + wb * E;
+      cm.sym_base = wo0 * E + wb * E;
       cm.out_base = so + wb * N;
       cm.n_windows = (int32_t)nwc;
       cm.out_len = (int32_t)ol;
@@ -314,8 +365,8 @@ __global__ void __launch_bounds__(kScanThreads) k_plan_stream_scan(fptc_batch b,
       meta[c0 + i] = cm;
     }
   }
-  const int64_t g0 = seg_off[s], ng = seg_off[s + 1] - g0;
-  if (seg_off[s + 1] > seg_cap) {  // word ranges of streams overlap: no segment room
+  const int64_t ng = g1 - g0;
+  if (g1 > seg_cap) {  // word ranges of streams overlap: no segment room
     if (threadIdx.x == 0 && status) atomicOr(&status[s], FPTC_STREAM_BAD_HEADER);
     return;  // its chunks keep first_word = -1
   }
@@ -336,11 +387,10 @@ __global__ void __launch_bounds__(kScanThreads) k_plan_stream_scan(fptc_batch b,
 // first symbol of a chunk (a multiple of wpc * E) becomes that chunk's first
 // word (the chunk before it ends at that word, inclusive when the chunk
 // starts inside the word).
-__global__ void __launch_bounds__(kScanThreads) k_plan_seg_chunks(fptc_batch b, int E, int wpc, const int64_t *hdr,
+__global__ void __launch_bounds__(kChunkThreads) k_plan_seg_chunks(fptc_batch b, int E, int wpc, const int64_t *hdr,
                                                                   const int64_t *chunk_off, const int64_t *seg_off,
                                                                   const int32_t *seg_stream,
                                                                   const int64_t *seg_base, ChunkMeta *meta) {
-  __shared__ int lds[kScanThreads / kWave];
   if (b.n_streams <= 0) return;
   const int64_t g = blockIdx.x;
   // as in k_plan_seg_sums: the stream index is clamped before any read with it
@@ -352,21 +402,20 @@ __global__ void __launch_bounds__(kScanThreads) k_plan_seg_chunks(fptc_batch b, 
   const int64_t c0 = chunk_off[s], nc = chunk_off[s + 1] - c0;
   pin(t.w0), pin(t.w1), pin(t.g0), pin(t.g1), pin(h2), pin(seg_cap), pin(gb), pin(c0), pin(nc);
   if (g >= h2 || t.g1 > seg_cap) return;  // past the plan, or the stream's segments did not fit (flagged)
-  SegWords sw;
+  constexpr int WPT = kSegWords / kChunkThreads;
+  __shared__ int lds[kChunkThreads / kWave];
+  SegWords<WPT> sw;
   load_seg_words(b, g, t, sw);
-  int sum = 0;
-#pragma unroll
-  for (int j = 0; j < kWordsPerThread; ++j) sum += sw.cnt[j];
   int tot;
-  const int ex = block_excl_scan_dpp(sum, lds, tot);
+  const int ex = block_excl_scan_dpp(seg_words_sum(sw), lds, tot);
   const int64_t cb = (int64_t)wpc * E;  // symbols per chunk
   int64_t p = gb + ex;
   // the boundaries inside this thread's words, from the first at or after p
   int64_t m = (p + cb - 1) / cb;
   int64_t mb = m * cb;
 #pragma unroll
-  for (int j = 0; j < kWordsPerThread; ++j) {
-    const int c = sw.cnt[j];
+  for (int j = 0; j < WPT; ++j) {
+    const int c = sw.cnt(j);
     for (; mb < p + c && m < nc; ++m, mb += cb) {
       const int64_t w = sw.first + j;
       // first word, first symbol and the last flag: one 16-byte store (the
@@ -388,14 +437,14 @@ int launch_plan(const fptc_batch &b, const fptc_codec &c, const Shape &s, const 
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return (int)e;
   const unsigned nseg = (unsigned)(p.seg_cap > 0 ? p.seg_cap : 1);  // blocks past hdr[2] exit at once
-  hipLaunchKernelGGL(k_plan_seg_sums, dim3(nseg), dim3(kScanThreads), 0, st, b, p.hdr, p.seg_off, p.seg_stream,
+  hipLaunchKernelGGL(k_plan_seg_sums, dim3(nseg), dim3(kSumThreads), 0, st, b, p.hdr, p.seg_off, p.seg_stream,
                      p.seg_sum, status);
   if ((e = hipGetLastError()) != hipSuccess) return (int)e;
   hipLaunchKernelGGL(k_plan_stream_scan, dim3(b.n_streams), dim3(kScanThreads), 0, st, b, c.N, c.E, s.wpc,
                      p.win_off, p.chunk_off, p.seg_off, p.seg_cap, p.seg_sum, p.seg_base, p.tile_stream, p.tile_cap,
                      p.chunk_meta, status);
   if ((e = hipGetLastError()) != hipSuccess) return (int)e;
-  hipLaunchKernelGGL(k_plan_seg_chunks, dim3(nseg), dim3(kScanThreads), 0, st, b, c.E, s.wpc, p.hdr, p.chunk_off,
+  hipLaunchKernelGGL(k_plan_seg_chunks, dim3(nseg), dim3(kChunkThreads), 0, st, b, c.E, s.wpc, p.hdr, p.chunk_off,
                      p.seg_off, p.seg_stream, p.seg_base, p.chunk_meta);
   return (int)hipGetLastError();
 }
