@@ -293,7 +293,7 @@ __device__ inline int seg_excl_scan(int v, int &total) {
   return incl - v;
 }
 
-// One workgroup per segment: the segment's symbol count (symlen clamped to
+// One wavefront per segment: the segment's symbol count (symlen clamped to
 // 64; a larger symlen is flagged).
 __global__ void __launch_bounds__(kSumThreads) k_plan_seg_sums(fptc_batch b, const int64_t *hdr,
                                                                 const int64_t *seg_off, const int32_t *seg_stream,
@@ -311,7 +311,7 @@ __global__ void __launch_bounds__(kSumThreads) k_plan_seg_sums(fptc_batch b, con
   SegWords<kSegWords / kSumThreads> sw;
   const int bad = load_seg_words(b, g, t, sw);
   int tot;
-  seg_excl_scan(seg_words_sum(sw), tot);
+  seg_excl_scan(seg_words_sum(sw), tot);  // only the wave's total is kept
   if (threadIdx.x == 0) seg_sum[g] = tot;
   if (bad && status) atomicOr(&status[s], bad);
 }
