@@ -108,7 +108,6 @@ __global__ void __launch_bounds__(64 * max_fused_waves(NT * 32)) k_fused(const u
   const int hs = 32 - lmax;  // peek = top lmax bits of the word = hi32 >> hs
   const float oscale = 1.0f / (T::kF16 ? kBasisScaleF16 : 1.0f);
   const int64_t n_chunks = hdr[0];
-  const int64_t cstride = (int64_t)gridDim.x * waves;
 
   // Software pipeline over this wave's chunks (taken from the workgroup's
   // schedule): the words of chunk i+1 (and the record of chunk i+2) are
@@ -116,7 +115,15 @@ __global__ void __launch_bounds__(64 * max_fused_waves(NT * 32)) k_fused(const u
   // decode, before chunk i's stores.  Vector memory counters retire in order,
   // so this one wait also covers chunk i-1's stores, which had the whole
   // decode to drain.
-  const BlockChunks sched{chunk_ctr, (int64_t)blockIdx.x * waves, cstride, 1, waves};
+  //
+  // The workgroup owns groups of kChunkGroup adjacent chunks spread over the
+  // whole batch (group g goes to workgroup g mod grid size).  Decode cost
+  // varies with the stream's bit rate, so many small groups from everywhere
+  // even out the workgroups' totals; within a group, adjacent chunks keep
+  // the words read and the samples written contiguous.
+  constexpr int kChunkGroup = 4;
+  const BlockChunks sched{chunk_ctr, (int64_t)blockIdx.x * kChunkGroup, (int64_t)gridDim.x * kChunkGroup, 1,
+                          kChunkGroup};
   int64_t c = sched.next(lane), cn = sched.next(lane);
   ChunkMeta cm = meta_from_lanes(load_meta_lane(meta, c, n_chunks, lane), c < n_chunks);
   const uint32_t vn = load_meta_lane(meta, cn, n_chunks, lane);

@@ -455,25 +455,26 @@ __device__ inline ChunkMeta meta_from_lanes(uint32_t d, bool valid) {
   }
   return m;
 }
-// Chunk schedule of a persistent workgroup: in each round of `stride` chunks
-// (workgroups x waves) it takes base + j step (j < waves), in increasing
-// order, handed out one at a time through a counter in LDS.  step 1 keeps a
-// round's chunks of one workgroup adjacent (neighbouring output and input);
-// step = the number of workgroups draws them from many streams, so that the
-// rounds' costs even out across workgroups.  A SIMD's arbiter favours its older
-// waves, so with a fixed share per wave the younger ones fall behind and
-// finish last while the older ones leave their SIMDs half empty; with the
-// shared counter a wave takes the next chunk whenever it is ready.  Indices
-// only grow, so a wave stops at the first one past the end.
+// Chunk schedule of a persistent workgroup: in each of its rounds it takes
+// per_round chunks, base + j step (j < per_round), the rounds `stride` chunks
+// apart, in increasing order, handed out one at a time through a counter in
+// LDS.  step 1 keeps a round's chunks adjacent (neighbouring output and
+// input); step = the number of workgroups draws them from many streams, so
+// that the rounds' costs even out across workgroups; small rounds of adjacent
+// chunks do both.  A SIMD's arbiter favours its older waves, so with a fixed
+// share per wave the younger ones fall behind and finish last while the older
+// ones leave their SIMDs half empty; with the shared counter a wave takes the
+// next chunk whenever it is ready.  Indices only grow, so a wave stops at the
+// first one past the end.
 struct BlockChunks {
   unsigned *ctr;  // LDS, zeroed before the loop
   int64_t base, stride, step;
-  int waves;
+  int per_round;
   __device__ int64_t next(int lane) const {
     unsigned t = 0;
     if (lane == 0) t = atomicAdd(ctr, 1u);
     t = __builtin_amdgcn_readfirstlane(t);
-    return base + (int64_t)(t % (unsigned)waves) * step + (int64_t)(t / (unsigned)waves) * stride;
+    return base + (int64_t)(t % (unsigned)per_round) * step + (int64_t)(t / (unsigned)per_round) * stride;
   }
 };
 
