@@ -186,13 +186,11 @@ __device__ inline void pin(int64_t x) { asm volatile("" ::"s"(x)); }
 // The segment's stream and its word range, loaded together with everything
 // else the kernel needs of the stream, before any check waits on them.
 struct SegStream {
-  int s;
   int64_t w0, w1, g0, g1;  // the stream's words, its segments
 };
 
 __device__ inline SegStream seg_stream_of(const fptc_batch &b, int s, const int64_t *seg_off) {
   SegStream t;
-  t.s = s;
   t.w0 = b.word_off[s];
   t.w1 = b.word_off[s + 1];
   t.g0 = seg_off[s];
