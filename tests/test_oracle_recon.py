@@ -122,3 +122,99 @@ def test_adam_refit_lowers_loss(O):
     gamma, losses = O.adam_refit(streams, p, steps=20)
     assert losses[-1] <= losses[0]
     assert gamma.shape == (2, 3)
+
+
+def _refit_streams(O):
+    streams = []
+    for i, dom in enumerate(["power", "meteo", "power"]):
+        p, x, sym = _stream(O, dom, 128 * 16, N=128, E=128, seed=i)
+        streams.append((sym, x))
+    return p, streams
+
+
+def _gamma_star(O, p, sym, x):
+    """Closed-form optimum of the separable quadratic loss of one stream
+    (zones disjoint, basis orthonormal, L a multiple of N): per zone,
+    sum v X / sum v^2 over that zone's coefficients; 1 where a zone is empty."""
+    X = O.dct_stream(x, p.N, p.E)
+    v, zt = O.dequant_table(p)
+    kk = np.tile(np.arange(p.E), x.size // p.N)
+    vv, zz = v[kk, sym], zt[kk, sym]
+    g = np.ones(3)
+    for z in range(3):
+        den = np.sum(vv[zz == z] ** 2)
+        if den > 0:
+            g[z] = np.sum(vv[zz == z] * X[zz == z]) / den
+    return g
+
+
+def test_adam_first_step_closed_form(O):
+    # At t = 1 both moment estimates are exact after bias correction
+    # (m_hat = g, v_hat = g^2), so Adam moves every scale by exactly
+    # lr * g / (|g| + eps): a step of about lr against the gradient's sign,
+    # and none where the gradient is zero.
+    p, streams = _refit_streams(O)
+    M = sum(x.size for _, x in streams)
+    lr, eps = 1e-2, 1e-8
+    gamma, losses = O.adam_refit(streams, p, steps=1, lr=lr, eps=eps)
+    for i, (sym, x) in enumerate(streams):
+        d = O.reconstruct(sym, x.size, p, np.ones(3)) - x.astype(np.float64)
+        _, g = O.backward(sym, x.size, p, 2.0 * d / M, want_coef=False)
+        expect = 1.0 - lr * g / (np.abs(g) + eps)
+        np.testing.assert_allclose(gamma[i], expect, rtol=0, atol=1e-15)
+        assert gamma[i][0] == 1.0  # zone 0 is the zero level: v == 0, no gradient
+    assert len(losses) == 2
+
+
+def test_adam_refit_matches_torch_adam_fp64(O):
+    # Same 20 full-batch steps with torch.optim.Adam (FP64, CPU) fed the
+    # oracle's gradients: an independent implementation of the update rule
+    # (bias corrections, beta1/beta2 roles, eps outside the square root).
+    import torch
+    p, streams = _refit_streams(O)
+    M = sum(x.size for _, x in streams)
+    gamma, losses = O.adam_refit(streams, p, steps=20)
+    gt = torch.ones((len(streams), 3), dtype=torch.float64, requires_grad=True)
+    opt = torch.optim.Adam([gt], lr=1e-2, betas=(0.9, 0.999), eps=1e-8)
+    tl = []
+    for _ in range(20):
+        opt.zero_grad()
+        g = np.zeros((len(streams), 3))
+        loss = 0.0
+        cur = gt.detach().numpy().copy()
+        for i, (sym, x) in enumerate(streams):
+            d = O.reconstruct(sym, x.size, p, cur[i]) - x.astype(np.float64)
+            loss += float(np.sum(d * d))
+            g[i] = O.backward(sym, x.size, p, 2.0 * d / M, want_coef=False)[1]
+        tl.append(loss / M)
+        gt.grad = torch.from_numpy(g)
+        opt.step()
+    np.testing.assert_allclose(gamma, gt.detach().numpy(), rtol=1e-12, atol=1e-12)
+    np.testing.assert_allclose(losses[:20], tl, rtol=1e-12)
+
+
+def test_adam_refit_bounded_by_closed_form_optimum(O):
+    # The loss is a separable quadratic in gamma with a closed-form minimum
+    # L(gamma*), so no iterate may go below it; 20 steps of lr 1e-2 from
+    # gamma = 1 must also close part of the gap.
+    p, streams = _refit_streams(O)
+    M = sum(x.size for _, x in streams)
+    gamma, losses = O.adam_refit(streams, p, steps=20)
+    lstar = 0.0
+    gs = []
+    for sym, x in streams:
+        g = _gamma_star(O, p, sym, x)
+        gs.append(g)
+        lstar += float(np.sum((O.reconstruct(sym, x.size, p, g) - x.astype(np.float64)) ** 2))
+    lstar /= M
+    assert all(l >= lstar * (1 - 1e-12) for l in losses)
+    assert losses[-1] < losses[0]
+    assert losses[-1] - lstar < losses[0] - lstar
+    # a zone whose optimum lies far from 1 (beyond what the steps can overshoot)
+    # has moved toward it
+    gs = np.array(gs)
+    far = np.abs(gs - 1.0) > 0.05
+    assert far.any()
+    assert np.all(np.sign(gamma - 1.0)[far] == np.sign(gs - 1.0)[far])
+    assert np.all(np.abs(gamma - gs)[far] < np.abs(1.0 - gs)[far])
+    print(f"L(gamma=1) {losses[0]:.6e}  L(after 20 Adam steps) {losses[-1]:.6e}  L(gamma*) {lstar:.6e}")
