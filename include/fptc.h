@@ -120,7 +120,9 @@ typedef struct {
                                  N >= 128); at most 16 (fused: 8 at N >= 128, else
                                  FPTC_ERR_UNSUPPORTED) */
   int32_t blocks;             /* persistent grid size; default: enough to fill the GPU */
-  int32_t reserved0;
+  int32_t chunk_group;        /* fptc_decompress_batch at N <= 128: adjacent chunks per group, groups
+                                 dealt round-robin over the grid (group g to block g mod blocks);
+                                 0 = default (4), at most 64 */
 } fptc_launch;
 
 /* Quantizer description for the host table builders and host encoder
@@ -146,6 +148,15 @@ FPTC_API int32_t fptc_abi_version(void);
 FPTC_API const char *fptc_status_string(int32_t status);
 
 /* --------------------------------------------------------- device calls */
+
+/* Set up the library on the current device: every kernel is allowed the
+ * whole 160 KB of a compute unit's LDS.  Done once per device and
+ * thread-safe; every device call below runs it on its first use with a
+ * device current, so calling it is optional.  Call it before capturing
+ * library calls into a HIP graph: the captured calls then make no runtime
+ * call besides their kernel launches.  FPTC_ERR_HIP when no device is
+ * current or an attribute is refused. */
+FPTC_API int32_t fptc_init(void);
 
 /* Bytes of device workspace the calls below need for this batch, codec and
  * launch shape (plan tables, chunk tables, backward partial sums).  0 on

@@ -105,12 +105,14 @@ class DeviceBatch:
 
 @dataclass
 class Launch:
-    windows_per_chunk: int = 32
-    waves_per_block: int = 0  # 0 = library default
+    """Launch shape of include/fptc.h's fptc_launch; 0 = library default."""
+    windows_per_chunk: int = 0
+    waves_per_block: int = 0
     blocks: int = 0
+    chunk_group: int = 0
 
     def c(self) -> F.fptc_launch:
-        return F.fptc_launch(self.windows_per_chunk, self.waves_per_block, self.blocks, 0)
+        return F.fptc_launch(self.windows_per_chunk, self.waves_per_block, self.blocks, self.chunk_group)
 
 
 class Decoder:

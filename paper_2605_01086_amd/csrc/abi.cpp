@@ -38,7 +38,9 @@ int resolve_shape(const fptc_launch *l, const fptc_codec *c, Shape *s) {
   s->waves = (l && l->waves_per_block) ? l->waves_per_block : kDefaultWavesPerBlock;
   s->auto_waves = !(l && l->waves_per_block);
   s->blocks = l ? l->blocks : 0;
+  s->group = (l && l->chunk_group) ? l->chunk_group : kDefaultChunkGroup;
   if (s->wpc < 1 || s->wpc > 1024 || s->waves < 1 || s->waves > 16 || s->blocks < 0) return FPTC_ERR_INVALID_ARG;
+  if (s->group < 1 || s->group > 64) return FPTC_ERR_INVALID_ARG;
   (void)c;
   return FPTC_OK;
 }
@@ -125,6 +127,8 @@ using namespace fptc;
 
 extern "C" {
 
+int32_t fptc_init(void) { return ensure_device_init() ? FPTC_ERR_HIP : FPTC_OK; }
+
 size_t fptc_workspace_size(const fptc_batch *batch, const fptc_codec *codec, const fptc_launch *launch) {
   Shape s;
   if (check_batch(batch) || check_codec(codec) || resolve_shape(launch, codec, &s)) return 0;
@@ -139,6 +143,7 @@ int32_t fptc_plan_batch(const fptc_batch *batch, const fptc_codec *codec, const 
   if (!ws) return FPTC_ERR_INVALID_ARG;
   Layout L = layout_for(batch, codec, s);
   if (ws_bytes < L.total) return FPTC_ERR_WORKSPACE;
+  if (ensure_device_init()) return FPTC_ERR_HIP;
   return status_of(launch_plan(*batch, *codec, s, plan_view(ws, L), stream_status, stream));
 }
 
@@ -156,6 +161,7 @@ int32_t fptc_decode_batch(const fptc_batch *batch, const fptc_codec *codec, cons
   if (decode_lds_bytes(*codec, s) > 160 * 1024) return FPTC_ERR_UNSUPPORTED;
   Layout L = layout_for(batch, codec, s);
   if (ws_bytes < L.total) return FPTC_ERR_WORKSPACE;
+  if (ensure_device_init()) return FPTC_ERR_HIP;
   return status_of(
       launch_decode(*batch, *codec, s, plan_view(const_cast<void *>(ws), L), symbols_out, stream_status, stream));
 }
@@ -174,6 +180,7 @@ int32_t fptc_dequant_idct(const fptc_batch *batch, const fptc_codec *codec, cons
     return FPTC_ERR_UNSUPPORTED;
   Layout L = layout_for(batch, codec, s);
   if (ws_bytes < L.total) return FPTC_ERR_WORKSPACE;
+  if (ensure_device_init()) return FPTC_ERR_HIP;
   Plan pv = plan_view(const_cast<void *>(ws), L);
   if (precision == FPTC_FP32_SIMT)
     return status_of(launch_dqidct(*batch, *codec, s, pv, symbols, gamma, precision, out, stream));
@@ -192,6 +199,7 @@ int32_t fptc_dequant_idct_backward(const fptc_batch *batch, const fptc_codec *co
   if (bwd_lds_bytes(*codec, s) > 160 * 1024) return FPTC_ERR_UNSUPPORTED;
   Layout L = layout_for(batch, codec, s);
   if (ws_bytes < L.total) return FPTC_ERR_WORKSPACE;
+  if (ensure_device_init()) return FPTC_ERR_HIP;
   return status_of(launch_bwd(*batch, *codec, s, plan_view(ws, L), symbols, grad_out, grad_coeff, grad_gamma, stream));
 }
 
@@ -216,6 +224,7 @@ int32_t fptc_decompress_batch(const fptc_batch *batch, const fptc_codec *codec, 
   if (!fits(s.waves)) return FPTC_ERR_UNSUPPORTED;
   Layout L = layout_for(batch, codec, s);
   if (ws_bytes < L.total) return FPTC_ERR_WORKSPACE;
+  if (ensure_device_init()) return FPTC_ERR_HIP;
   Plan pv = plan_view(const_cast<void *>(ws), L);
   if (wide) return status_of(launch_fused256(*batch, *codec, s, pv, gamma, precision, out, stream_status, stream));
   return status_of(launch_fused(*batch, *codec, s, pv, gamma, precision, out, stream_status, stream));

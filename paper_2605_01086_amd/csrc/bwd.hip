@@ -110,6 +110,8 @@ __global__ void k_bwd_streams(int n_streams, const int64_t *chunk_off, const Chu
 
 }  // namespace
 
+int set_bwd_attributes() { return lds_attr(k_bwd_chunk); }
+
 size_t bwd_lds_bytes(const fptc_codec &c, const Shape &s) {
   const int KB = bwd_bins_per_block(c.N);
   return sizeof(float) * ((size_t)s.wpc * c.N + (size_t)c.N * KB) + sizeof(double) * 3 * kThreads;
@@ -119,13 +121,6 @@ int launch_bwd(const fptc_batch &b, const fptc_codec &c, const Shape &s, const P
                const float *grad_out, float *grad_coeff, double *grad_gamma, void *stream) {
   hipStream_t st = (hipStream_t)stream;
   const size_t lds = bwd_lds_bytes(c, s);
-  static bool attr_set = false;
-  if (!attr_set) {
-    if (hipFuncSetAttribute(reinterpret_cast<const void *>(k_bwd_chunk), hipFuncAttributeMaxDynamicSharedMemorySize,
-                            160 * 1024) != hipSuccess)
-      return (int)hipErrorInvalidValue;
-    attr_set = true;
-  }
   const int per_cu = (int)((160 * 1024) / lds);
   const int blocks = s.blocks > 0 ? s.blocks : device_cu_count() * (per_cu < 1 ? 1 : (per_cu > 8 ? 8 : per_cu));
   hipLaunchKernelGGL(k_bwd_chunk, dim3(blocks), dim3(kThreads), lds, st, b, c.N, c.E, s.wpc, c.n_books, c.n_rows,

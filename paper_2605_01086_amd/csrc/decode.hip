@@ -132,13 +132,6 @@ int launch_t(const fptc_batch &b, const fptc_codec &c, const Shape &s, const Pla
              int32_t *status, void *stream) {
   const int threads = s.waves * kWave;
   const size_t lds = decode_lds(MS, c.n_books, c.lmax, s.wpc, c.E, s.waves);
-  static bool attr_set = false;
-  if (!attr_set) {
-    if (hipFuncSetAttribute(reinterpret_cast<const void *>(k_decode<MS>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024) != hipSuccess)
-      return (int)hipErrorInvalidValue;
-    attr_set = true;
-  }
   const int per_cu = (int)((160 * 1024) / lds);
   int blocks = s.blocks > 0 ? s.blocks : device_cu_count() * (per_cu < 1 ? 1 : (per_cu > 8 ? 8 : per_cu));
   hipLaunchKernelGGL(k_decode<MS>, dim3(blocks), dim3(threads), lds, (hipStream_t)stream, b.words, b.symlen,
@@ -148,6 +141,10 @@ int launch_t(const fptc_batch &b, const fptc_codec &c, const Shape &s, const Pla
 }
 
 }  // namespace
+
+int set_decode_attributes() {
+  return lds_attr(k_decode<true>) | lds_attr(k_decode<false>);
+}
 
 // The smaller (single-symbol) layout: what the launch needs at least.
 size_t decode_lds_bytes(const fptc_codec &c, const Shape &s) {

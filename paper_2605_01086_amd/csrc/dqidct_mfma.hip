@@ -226,13 +226,6 @@ int launch_t(const fptc_batch &b, const fptc_codec &c, const Shape &sh, const Pl
   const int S = (c.E + 15) / 16, Kp = S * 16;
   const size_t lds = mfma_lds_bytes(Traits<PREC>::kBPieces, N, Kp, c.n_books, c.n_rows, c.E);
   auto kern = k_dqidct_mfma<PREC, NT>;
-  static bool attr_set = false;  // one attribute call per instantiation
-  if (!attr_set) {
-    if (hipFuncSetAttribute(reinterpret_cast<const void *>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
-                            160 * 1024) != hipSuccess)
-      return (int)hipErrorInvalidValue;
-    attr_set = true;
-  }
   const int per_cu = (int)((160 * 1024) / lds);
   int blocks = sh.blocks > 0 ? sh.blocks : device_cu_count() * (per_cu < 1 ? 1 : (per_cu > 8 ? 8 : per_cu));
   hipLaunchKernelGGL(kern, dim3(blocks), dim3(kThreads), lds, (hipStream_t)stream, b, c.E, S, c.n_books, c.n_rows,
@@ -251,7 +244,16 @@ int launch_prec(const fptc_batch &b, const fptc_codec &c, const Shape &sh, const
   }
 }
 
+template <int PREC>
+int attrs_prec() {
+  return lds_attr(k_dqidct_mfma<PREC, 1>) | lds_attr(k_dqidct_mfma<PREC, 2>) | lds_attr(k_dqidct_mfma<PREC, 4>);
+}
+
 }  // namespace
+
+int set_dqidct_mfma_attributes() {
+  return attrs_prec<FPTC_FP16>() | attrs_prec<FPTC_FP16X2>() | attrs_prec<FPTC_BF16>() | attrs_prec<FPTC_BF16X3>();
+}
 
 bool mfma_supported(int N, int E, int precision, int n_books, int n_rows) {
   if (precision < FPTC_FP16 || precision > FPTC_BF16X3) return false;

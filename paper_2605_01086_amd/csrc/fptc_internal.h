@@ -12,6 +12,7 @@ namespace fptc {
 constexpr int kWave = 64;
 constexpr int kDefaultWindowsPerChunk = 32;
 constexpr int kDefaultWavesPerBlock = 4;
+constexpr int kDefaultChunkGroup = 4;
 constexpr int kMaxBooks = 8;
 constexpr int kMaxRows = 4;
 constexpr int kMaxLmax = 12;
@@ -42,6 +43,7 @@ struct Shape {
   int wpc;     // windows per chunk
   int waves;   // waves per block
   int blocks;  // persistent grid size (0 = launcher decides)
+  int group;   // fused schedule: adjacent chunks per group
   bool auto_waves;  // waves_per_block was 0: each call may pick its own
 };
 
@@ -108,5 +110,27 @@ int launch_bwd(const fptc_batch &b, const fptc_codec &c, const Shape &s, const P
                const float *grad_out, float *grad_coeff, double *grad_gamma, void *stream);
 
 int device_cu_count();
+
+// Library set-up on the current device, once per device (thread-safe):
+// kernel attributes (dynamic LDS up to 160 KB) for every kernel
+// instantiation.  Every device entry point runs it before enqueueing, so the
+// launches themselves are the only runtime calls a call makes afterwards.
+int ensure_device_init();
+int set_decode_attributes();
+int set_dqidct_mfma_attributes();
+int set_fused_attributes();
+int set_mfma256_attributes();
+int set_bwd_attributes();
+
+#ifdef __HIPCC__
+// Allow a kernel the whole 160 KB of a CU's LDS as dynamic shared memory.
+template <typename K>
+int lds_attr(K kern) {
+  return hipFuncSetAttribute(reinterpret_cast<const void *>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
+                             160 * 1024) == hipSuccess
+             ? 0
+             : 1;
+}
+#endif
 
 }  // namespace fptc

@@ -67,7 +67,7 @@ __global__ void __launch_bounds__(64 * max_fused_waves(NT * 32)) k_fused(const u
                                                             const int64_t *__restrict__ hdr,
                                                             const ChunkMeta *__restrict__ meta,
                                                             const float *__restrict__ gamma, float *out,
-                                                            int32_t *status) {
+                                                            int32_t *status, int group) {
   using T = Traits<PREC>;
   constexpr int N = NT * 32;
   const int Kp = S * 16, KH = Kp / 2, RS = Kp + 8;
@@ -116,14 +116,12 @@ __global__ void __launch_bounds__(64 * max_fused_waves(NT * 32)) k_fused(const u
   // so this one wait also covers chunk i-1's stores, which had the whole
   // decode to drain.
   //
-  // The workgroup owns groups of kChunkGroup adjacent chunks spread over the
+  // The workgroup owns groups of `group` adjacent chunks spread over the
   // whole batch (group g goes to workgroup g mod grid size).  Decode cost
   // varies with the stream's bit rate, so many small groups from everywhere
   // even out the workgroups' totals; within a group, adjacent chunks keep
   // the words read and the samples written contiguous.
-  constexpr int kChunkGroup = 4;
-  const BlockChunks sched{chunk_ctr, (int64_t)blockIdx.x * kChunkGroup, (int64_t)gridDim.x * kChunkGroup, 1,
-                          kChunkGroup};
+  const BlockChunks sched{chunk_ctr, (int64_t)blockIdx.x * group, (int64_t)gridDim.x * group, 1, group};
   int64_t c = sched.next(lane), cn = sched.next(lane);
   ChunkMeta cm = meta_from_lanes(load_meta_lane(meta, c, n_chunks, lane), c < n_chunks);
   const uint32_t vn = load_meta_lane(meta, cn, n_chunks, lane);
@@ -204,18 +202,11 @@ int launch_t(const fptc_batch &b, const fptc_codec &c, const Shape &sh, const Pl
   const size_t lds =
       fused_lds_bytes(MS, Traits<PREC>::kBPieces, N, c.E, Kp, sh.wpc, sh.waves, c.n_books, c.n_rows, c.lmax);
   auto kern = k_fused<PREC, NT, MS>;
-  static bool attr_set = false;  // one attribute call per instantiation
-  if (!attr_set) {
-    if (hipFuncSetAttribute(reinterpret_cast<const void *>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
-                            160 * 1024) != hipSuccess)
-      return (int)hipErrorInvalidValue;
-    attr_set = true;
-  }
   const int per_cu = (int)((160 * 1024) / lds);
   const int blocks = sh.blocks > 0 ? sh.blocks : device_cu_count() * (per_cu > 0 ? per_cu : 1);
   hipLaunchKernelGGL(kern, dim3(blocks), dim3(sh.waves * 64), lds, (hipStream_t)stream, b.words, b.symlen,
                      b.n_streams, c.E, S, c.lmax, c.n_books, c.n_rows, sh.wpc, c.lut, c.deq_val, c.deq_zone,
-                     c.row_of_bin, c.basis, p.hdr, p.chunk_meta, gamma, out, status);
+                     c.row_of_bin, c.basis, p.hdr, p.chunk_meta, gamma, out, status, sh.group);
   return (int)hipGetLastError();
 }
 
@@ -241,7 +232,21 @@ int launch_prec(const fptc_batch &b, const fptc_codec &c, const Shape &sh, const
   }
 }
 
+template <int PREC, int NT>
+int attrs_nt() {
+  return lds_attr(k_fused<PREC, NT, true>) | lds_attr(k_fused<PREC, NT, false>);
+}
+
+template <int PREC>
+int attrs_prec() {
+  return attrs_nt<PREC, 1>() | attrs_nt<PREC, 2>() | attrs_nt<PREC, 4>();
+}
+
 }  // namespace
+
+int set_fused_attributes() {
+  return attrs_prec<FPTC_FP16>() | attrs_prec<FPTC_FP16X2>() | attrs_prec<FPTC_BF16>() | attrs_prec<FPTC_BF16X3>();
+}
 
 bool fused_supported(int N, int E, int precision, int wpc, int waves, int n_books, int n_rows, int lmax) {
   if (precision < FPTC_FP16 || precision > FPTC_BF16X3) return false;

@@ -355,10 +355,9 @@ size_t fused256_lds(int bp, const fptc_codec &c, int wpc, int waves, int n_rows)
   return fused256_lds_ms(false, bp, c.n_books, c.lmax, c.E, wpc, waves, n_rows);
 }
 
-template <typename K>
-bool set_lds_attr(K kern) {
-  return hipFuncSetAttribute(reinterpret_cast<const void *>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
-                             160 * 1024) == hipSuccess;
+template <int PREC>
+int attrs_prec() {
+  return lds_attr(k_dqidct_mfma256<PREC>) | lds_attr(k_fused256<PREC, true>) | lds_attr(k_fused256<PREC, false>);
 }
 
 // Split the basis into the workspace (one workgroup per staged block).
@@ -373,8 +372,6 @@ int split_basis(const fptc_codec &c, int S, const Plan &p, void *stream) {
 template <int PREC>
 int launch_split(const fptc_batch &b, const fptc_codec &c, const Shape &sh, const Plan &p, const uint8_t *symbols,
                  const float *gamma, float *out, void *stream) {
-  static bool attr = false;
-  if (!attr && !(attr = set_lds_attr(k_dqidct_mfma256<PREC>))) return (int)hipErrorInvalidValue;
   const int S = (c.E + 15) / 16;
   int rc = split_basis<PREC>(c, S, p, stream);
   if (rc) return rc;
@@ -390,8 +387,6 @@ int launch_split(const fptc_batch &b, const fptc_codec &c, const Shape &sh, cons
 template <int PREC, bool MS>
 int launch_fused_t(const fptc_batch &b, const fptc_codec &c, const Shape &sh, const Plan &p, const float *gamma,
                    float *out, int32_t *status, void *stream) {
-  static bool attr = false;
-  if (!attr && !(attr = set_lds_attr(k_fused256<PREC, MS>))) return (int)hipErrorInvalidValue;
   const int S = (c.E + 15) / 16;
   int rc = split_basis<PREC>(c, S, p, stream);
   if (rc) return rc;
@@ -416,6 +411,10 @@ int launch_fused_ms(const fptc_batch &b, const fptc_codec &c, const Shape &sh, c
 }
 
 }  // namespace
+
+int set_mfma256_attributes() {
+  return attrs_prec<FPTC_FP16>() | attrs_prec<FPTC_FP16X2>() | attrs_prec<FPTC_BF16>() | attrs_prec<FPTC_BF16X3>();
+}
 
 bool mfma256_supported(int E, int precision) {
   if (precision < FPTC_FP16 || precision > FPTC_BF16X3) return false;

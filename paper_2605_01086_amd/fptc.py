@@ -39,7 +39,7 @@ class fptc_codec(ctypes.Structure):
 
 class fptc_launch(ctypes.Structure):
     _fields_ = [("windows_per_chunk", ctypes.c_int32), ("waves_per_block", ctypes.c_int32),
-                ("blocks", ctypes.c_int32), ("reserved0", ctypes.c_int32)]
+                ("blocks", ctypes.c_int32), ("chunk_group", ctypes.c_int32)]
 
 
 class fptc_quant_params(ctypes.Structure):
@@ -54,6 +54,7 @@ _P = ctypes.POINTER
 _SIGS = {
     "fptc_abi_version": (ctypes.c_int32, []),
     "fptc_status_string": (ctypes.c_char_p, [ctypes.c_int32]),
+    "fptc_init": (ctypes.c_int32, []),
     "fptc_workspace_size": (ctypes.c_size_t, [_P(fptc_batch), _P(fptc_codec), _P(fptc_launch)]),
     "fptc_plan_batch": (ctypes.c_int32, [_P(fptc_batch), _P(fptc_codec), _P(fptc_launch), _vp, ctypes.c_size_t,
                                          _vp, _vp]),
@@ -141,6 +142,10 @@ def fptc_abi_version() -> int:
 
 def fptc_status_string(code: int) -> str:
     return status_string(code)
+
+
+def fptc_init() -> None:
+    _check("fptc_init", load().fptc_init())
 
 
 def fptc_workspace_size(batch: fptc_batch, codec: fptc_codec, launch: fptc_launch) -> int:

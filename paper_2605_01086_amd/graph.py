@@ -2,14 +2,14 @@
 or plan + decode + dequant/IDCT), replayed as one graph launch.
 
 The library's calls only enqueue kernels on the current stream (no host
-synchronisation, no allocation, no memset nodes), so a step captures as is.
-The first eager call of each entry point sets its kernel attributes; capture
-therefore follows a warm-up step.
+synchronisation, no allocation, no memset nodes) once the library is set up
+on the device, which fptc_init does before capture.
 """
 from __future__ import annotations
 
 import torch
 
+from . import fptc as F
 from .codec import Decoder
 
 
@@ -17,7 +17,7 @@ class CapturedStep:
     def __init__(self, decoder: Decoder, precision: str = "fp16x2", fused: bool = True, gamma=None):
         self.decoder = decoder
         self.args = dict(gamma=gamma, precision=precision, fused=fused)
-        decoder.run(**self.args)  # warm-up: kernel attributes, allocator state
+        F.fptc_init()
         torch.cuda.synchronize()
         self.graph = torch.cuda.CUDAGraph()
         s = torch.cuda.Stream()

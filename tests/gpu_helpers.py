@@ -59,9 +59,8 @@ def run_gpu(case: Case, launch=None, precision="fp32", use_gamma=True, words_ove
     return dict(sym=s_h[:batch.n_symbols], out=o_h[:batch.n_samples], status=st_h, batch=batch, runs=results)
 
 
-def _diagnose(case: Case, res, bad_stream: int) -> str:
-    """Describe which windows of which streams disagree; dump arrays for offline study."""
-    import os
+def _diagnose(case: Case, res) -> str:
+    """Describe which windows of which streams disagree."""
     batch = res["batch"]
     N = case.p.N
     lines = []
@@ -79,10 +78,6 @@ def _diagnose(case: Case, res, bad_stream: int) -> str:
                              f"(first {wins[:6].tolist()}), got {res['out'][o0 + bad[0]]:.4f} "
                              f"want {case.recon[i][bad[0]]:.4f}")
     lines.insert(0, f"{nbad_streams} of {len(case.signals)} streams disagree")
-    if os.path.isdir("gpurun_out"):
-        np.savez_compressed(f"gpurun_out/parity_fail_stream{bad_stream}.npz", out=res["out"], sym=res["sym"],
-                            recon=np.concatenate(case.recon) if case.recon else np.zeros(0),
-                            sample_off=batch.sample_off_h, sym_off=batch.sym_off_h)
     return "\n".join(lines)
 
 
@@ -102,5 +97,5 @@ def check_parity(case: Case, res, tol=1e-5, skip=(), check_symbols=True):
         err = range_rel_err(res["out"][o0:o1], case.recon[i])
         worst = max(worst, err)
         if err > tol:
-            raise AssertionError(f"stream {i}: range-relative error {err:.3e} > {tol}\n" + _diagnose(case, res, i))
+            raise AssertionError(f"stream {i}: range-relative error {err:.3e} > {tol}\n" + _diagnose(case, res))
     return worst

@@ -6,7 +6,9 @@ decodes and reconstructs those streams one by one).
   2^20, windows 64 and 256, every MFMA variant and FP32, max-abs and RMS error
   against FP64 reported per variant;
 * large multichannel workload: 64 channels x 2^24 EEG-like samples mixed by a
-  random matrix, window 256, steps 1.0 / 8.0, fused FP16X2 vs FP32."""
+  random matrix, window 256, steps 1.0 / 8.0, fused FP16X2 vs FP32;
+* batch workload: all 4096 streams (about 1.02e9 samples) compared with the
+  oracle stream by stream."""
 import numpy as np
 import pytest
 
@@ -124,3 +126,69 @@ def test_large_multichannel_workload_sampled():
             for out in (out_f, out_32):
                 got = out[o0:o0 + 4096 * 256]
                 assert np.abs(got - ref).max() <= 1e-5 * np.ptp(ref)
+
+
+@pytest.mark.timeout(900)
+def test_batch_workload_every_stream():
+    """The batch workload at full size (4096 streams of floor(2^U(14, 20))
+    samples, four signal domains with a codebook each, window 64): every
+    stream encoded by the oracle, decoded on the GPU in the launch shape the
+    benchmark times, and compared stream by stream with the oracle -- symbols
+    bit-exact (split path), reconstruction within 1e-5 of each stream's range
+    for FP32 SIMT (split) and FP16X2 (fused)."""
+    import os
+    import time
+    from concurrent.futures import ThreadPoolExecutor
+
+    import torch
+    from synth import workloads as W
+    from oracle import oracle as O
+    from paper_2605_01086_amd import codec as C
+    threads = max(1, min(16, len(os.sched_getaffinity(0))))
+    t0 = time.perf_counter()
+    w = W.workload("batch")
+    p = O.QuantParams("amp", 64, 64, step_f=0.25, step_c=2.0, T=16.0)
+    books = [O.train_codebook(O.quantize_stream(t, p)) for t in W.training_signals(w)]
+    x = W.signals(w, threads=threads)
+    off = w.sample_off
+
+    def enc_one(i):
+        return O.encode_stream(x[off[i]:off[i + 1]], p, books[w.book_id[i]])
+
+    with ThreadPoolExecutor(threads) as ex:
+        enc = list(ex.map(enc_one, range(w.n_streams)))
+    signals_len = [int(L) for L in w.lengths]
+    del x
+    t_enc = time.perf_counter() - t0
+    codec, batch = _device(p, books, [np.empty(L, np.float32) for L in signals_len], enc, w.book_id)
+    dec = C.Decoder(batch, codec)
+    dec.plan()
+    dec.decode()
+    split32 = dec.dequant_idct(precision="fp32").cpu().numpy()
+    fused = dec.decompress(precision="fp16x2").cpu().numpy()
+    status = dec.status.cpu().numpy()
+    symbols = dec.symbols.cpu().numpy()
+    torch.cuda.synchronize()
+    assert np.all(status == 0), np.flatnonzero(status)[:8]
+    so, yo = batch.sample_off_h, batch.sym_off_h
+
+    def check(i):
+        sym = enc[i][2]
+        if not np.array_equal(symbols[yo[i]:yo[i + 1]], sym):
+            return (i, "symbols", np.inf, np.inf)
+        ref = O.reconstruct(sym, signals_len[i], p)
+        rng = float(np.ptp(ref)) or 1.0
+        e32 = float(np.abs(split32[so[i]:so[i + 1]] - ref).max()) / rng
+        e16 = float(np.abs(fused[so[i]:so[i + 1]] - ref).max()) / rng
+        return (i, "ok", e32, e16)
+
+    with ThreadPoolExecutor(threads) as ex:
+        res = list(ex.map(check, range(w.n_streams)))
+    bad_sym = [r[0] for r in res if r[1] != "ok"]
+    assert not bad_sym, f"streams whose symbols differ from the oracle's: {bad_sym[:8]}"
+    e32 = np.array([r[2] for r in res])
+    e16 = np.array([r[3] for r in res])
+    print(f"\nbatch workload: {w.n_streams} streams, {int(off[-1])} samples, oracle encode {t_enc:.1f}s, "
+          f"total {time.perf_counter() - t0:.1f}s; worst range-relative error: FP32 split {e32.max():.3e} "
+          f"(stream {int(e32.argmax())}), FP16X2 fused {e16.max():.3e} (stream {int(e16.argmax())})")
+    assert e32.max() <= 1e-5 and e16.max() <= 1e-5

@@ -50,5 +50,8 @@ def test_graph_replays_match_eager(fused, precision):
 def test_autotune_candidates_agree():
     from paper_2605_01086_amd import autotune
     c, codec, batch = _setup(2500)
-    best, times = autotune.tune(batch, codec, "fp16x2", fused=True, use_cache=False)
-    assert len(times) >= 3 and best is not None
+    best, info = autotune.tune(batch, codec, "fp16x2", fused=True, use_cache=False)
+    measured = [v for v in info["times"].values() if v is not None]
+    assert len(measured) >= 6 and best is not None and not info["cached"]
+    # a coordinate moves only on a gain above 0.5 %, so no candidate beats the pick by more
+    assert info["best_ms"] * 0.995 <= min(measured) <= info["best_ms"]

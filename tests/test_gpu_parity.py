@@ -87,11 +87,27 @@ def test_corrupt_streams_are_flagged_and_isolated():
     sl[word_off[3] + 2] = 200                   # stream 3: symlen above 64
     w = words.copy()
     w[word_off[4]:word_off[4 + 1]] = ~np.uint64(0)  # stream 4: all-ones words
+    # all-ones bits parse as the longest canonical code over and over: the
+    # stream is an overrun exactly when the oracle's bit-serial decode of the
+    # same words and counts runs past bit 64 of some word
+    from oracle import oracle as O
+    try:
+        O.symlen_decode(w[word_off[4]:word_off[5]], c.symlen[4], c.books[c.book_id[4]], int(c.symlen[4].sum()))
+        over4 = False
+    except ValueError as e:
+        assert "-1" in str(e), str(e)
+        over4 = True
     res = run_gpu(c, words_override=w, symlen_override=sl)
     st = res["status"]
     assert st[1] & F.FPTC_STREAM_BAD_COUNT
     assert st[3] & F.FPTC_STREAM_BAD_SYMLEN
-    assert st[4] != 0 or True  # all-ones words may still parse; the other streams must be unaffected
+    assert bool(st[4] & F.FPTC_STREAM_OVERRUN) == over4, (int(st[4]), over4)
+    assert (int(st[4]) & ~F.FPTC_STREAM_OVERRUN) == 0, int(st[4])
+    if not over4:  # then the GPU's symbols are the oracle's parse of those words
+        ref = O.symlen_decode(w[word_off[4]:word_off[5]], c.symlen[4], c.books[c.book_id[4]],
+                              int(c.symlen[4].sum()))
+        s0, s1 = res["batch"].sym_off_h[4], res["batch"].sym_off_h[5]
+        assert np.array_equal(res["sym"][s0:s1], ref)
     check_parity(c, res, skip={1, 3, 4})
 
 
@@ -180,7 +196,7 @@ def test_short_stream_skips_the_chunks_no_word_reaches(fused):
     s_h, o_h, st = run(bad)
     assert st[1] & F.FPTC_STREAM_BAD_COUNT, int(st[1])
     assert st[0] == 0 and st[2] == 0, st
-    wpc = C.Launch().windows_per_chunk
+    wpc = 32  # the library's default windows per chunk
     cb = wpc * c.p.E  # symbols per chunk
     carry = int(np.minimum(sl[a:b], 64).astype(np.int64).sum())
     reached = -(-carry // cb)
