@@ -73,12 +73,31 @@ def cpu_model() -> str:
     return "unknown"
 
 
-def quant_for(name: str):
+def quant_for(name: str, w=None):
     from paper_2605_01086_amd import codec as C
     if name == "large":  # window 256, coarse steps 1.0 / 8.0
         return C.quant_params("amp", 256, 256, step_fine=1.0, step_coarse=8.0, threshold=THRESH)
+    if name == "paper":  # Table 1's typical values; A0 / A1 from the training data, on the GPU
+        return paper_quant(32, 16, w)
     N = {"plain": 64, "batch": 64, "grad": 128}.get(name, 64)
     return C.quant_params("amp", N, N, step_fine=STEP_F, step_coarse=STEP_C, threshold=THRESH)
+
+
+def paper_quant(N: int, E: int, w, B1: int = 2, B2: int | None = None):
+    """The paper quantizer (mu 50, alpha1 0.004) at window N keeping E bins,
+    zones [0, B1) mu-law, [B1, B2) deadzone (B2 = E by default, as Table 1's
+    N = 32, E = 16, B2 = 16), A0 / A1 the 99.9th percentile of |c| over the
+    workload's training signal."""
+    from paper_2605_01086_amd import codec as C
+    from synth import workloads as W
+    B1 = min(B1, E)
+    B2 = E if B2 is None else B2
+    q = C.quant_params("paper", N, E, B1=B1, B2=B2, mu=50.0, alpha1=0.004)
+    q.A0, q.A1 = C.zone_maxima(W.training_signals(w)[0], q, 99.9)
+    return q
+
+
+_SIGNALS = {}
 
 
 def encode(w, q, threads):
@@ -87,7 +106,11 @@ def encode(w, q, threads):
     from paper_2605_01086_amd import codec as C
     from paper_2605_01086_amd import fptc as F
     from synth import workloads as W
-    x = W.signals(w, threads)
+    x = _SIGNALS.get(w.name)
+    if x is None:
+        x = W.signals(w, threads)
+        if w.name == "sweep":  # every point of the sweep encodes the same signals
+            _SIGNALS[w.name] = x
     lens_tab = np.stack([C.train_code_lengths(t, q) for t in W.training_signals(w)])
     sample_off = w.sample_off
     nsym = C.n_windows(w.lengths, q.N) * q.E
@@ -115,7 +138,7 @@ class Setup:
         t0 = time.perf_counter()
         self.name = name
         self.w = W.workload(name)
-        self.q = q or quant_for(name)
+        self.q = q or quant_for(name, self.w)
         self.words, self.symlen, self.word_off, self.lens_tab = encode(self.w, self.q, threads)
         self.sample_off = self.w.sample_off
         self.codec = C.DeviceCodec(self.lens_tab, self.q, 12)
@@ -322,7 +345,9 @@ def time_per_stream(s: Setup, launch, steps, precision):
 
 def oracle_params(q):
     from oracle import oracle as O
-    return O.QuantParams("amp", q.N, q.E, step_f=q.step_fine, step_c=q.step_coarse, T=q.threshold)
+    if q.kind == 0:
+        return O.QuantParams("amp", q.N, q.E, step_f=q.step_fine, step_c=q.step_coarse, T=q.threshold)
+    return O.QuantParams("paper", q.N, q.E, B1=q.B1, B2=q.B2, mu=q.mu, alpha1=q.alpha1, A0=q.A0, A1=q.A1)
 
 
 def oracle_decode(s: Setup, i: int, keep: bool = False):
@@ -456,12 +481,45 @@ def leg_grad(s: Setup, launch, steps, warmup):
     return res, outs
 
 
+def sweep(threads, steps, warmup):
+    """Decoded GB/s over window N and kept coefficients E at the paper
+    quantizer (zones [0, 2) mu-law, [2, E) deadzone), on 128 EEG-like streams
+    of 2^20 samples: the fused FP16X2 path (N >= 32) and the split FP32 SIMT
+    path, graph-replayed steps."""
+    from paper_2605_01086_amd import codec as C
+    from synth import workloads as W
+    w = W.workload("sweep")
+    rows = []
+    for N in (16, 32, 64, 128):
+        for E in sorted({4, 8, 16, N // 2, N}):
+            if E > N:
+                continue
+            q = paper_quant(N, E, w)
+            s = Setup("sweep", threads, q)
+            row = {"N": N, "E": E, "bytes_per_sample_in": round(s.comp_bytes / s.n_samples, 4)}
+            if N >= 32:
+                dec, ms, _, per, _ = batched(s, C.Launch(), "fp16x2", True, steps, warmup)
+                row["fused_fp16x2_GBs"] = round(4 * s.n_samples / (ms * 1e-3) / 1e9, 1)
+                row["fused_ms"] = round(ms, 4)
+                row["fused_kernel_frac_hbm"] = roofline(s, "fused", per["fused"], "fp16x2", "sweep")["frac"]
+                del dec
+            dec, ms, _, per, _ = batched(s, C.Launch(), "fp32", False, steps, warmup)
+            row["split_fp32_GBs"] = round(4 * s.n_samples / (ms * 1e-3) / 1e9, 1)
+            row["split_ms"] = round(ms, 4)
+            row["split_stage_ms"] = {k: round(v, 4) for k, v in per.items()}
+            del dec, s
+            release()
+            rows.append(row)
+            log(f"sweep N={N} E={E}: {row}")
+    return rows
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="batch", choices=["batch", "plain", "precision", "grad", "large"],
+    ap.add_argument("--workload", default="batch", choices=["batch", "plain", "precision", "grad", "large", "paper"],
                     help="headline workload")
     ap.add_argument("--precision", default="fp16x2", choices=["fp32", "fp16", "fp16x2", "bf16", "bf16x3"])
     ap.add_argument("--path", default="fused", choices=["fused", "split"],
@@ -475,11 +533,13 @@ def main():
     ap.add_argument("--graph", dest="graph", action="store_true", default=True,
                     help="time the step as replays of one captured HIP graph (plan + decode kernels; default)")
     ap.add_argument("--no-graph", dest="graph", action="store_false", help="time eager launches instead")
-    ap.add_argument("--configs", default="plain,precision,grad,large",
+    ap.add_argument("--configs", default="plain,precision,grad,large,paper",
                     help="other workloads reported in the same line (comma list, or 'none')")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-per-stream", action="store_true")
+    ap.add_argument("--sweep", action="store_true",
+                    help="only run the sweep over window N and kept coefficients E at the paper quantizer")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB copy kernel (torch.neg) 3 times: the reference dispatch for "
                          "scaling rocprofv3 FETCH_SIZE / WRITE_SIZE readings to bytes")
@@ -504,6 +564,11 @@ def main():
 
     from paper_2605_01086_amd import codec as C
     threads = host_threads()
+    if args.sweep:
+        rows = sweep(threads, args.steps, args.warmup)
+        print(json.dumps({"sweep": rows, "workload": "128 EEG-like streams x 2^20 samples, paper quantizer",
+                          "steps": args.steps}), flush=True)
+        return
     s = Setup(args.workload, threads)
     fused = args.path == "fused"
     if fused and args.precision == "fp32":
@@ -628,7 +693,7 @@ def main():
                 entry["samples"] = cs.n_samples
                 del outs, cs
                 release()
-            elif name in ("plain", "large"):
+            elif name in ("plain", "large", "paper"):
                 cs = Setup(name, threads)
                 prec = ("fp16x2",)
                 entry, outs = leg_fused_vs_fp32(cs, C.Launch(), max(5, args.steps // 2), 2, prec, True)
@@ -636,11 +701,18 @@ def main():
                     if name == "plain":
                         entry["cpu_baseline_single_thread"] = cpu_oracle(cs, [0], 1)
                         entry["oracle_error"] = errors_vs_oracle(cs, outs, [0], 1)
+                    elif name == "paper":
+                        entry["oracle_error"] = errors_vs_oracle(cs, outs, [0, 1], 2)
+                        entry["oracle_error"]["streams"] = "streams 0 and 1"
                     else:
                         entry["oracle_error"] = errors_vs_oracle(cs, outs, [5], 1)
                         entry["oracle_error"]["streams"] = "channel 5"
                 entry["samples"] = cs.n_samples
                 entry["bytes_per_sample_in"] = round(cs.comp_bytes / cs.n_samples, 4)
+                if name == "paper":
+                    q = cs.q
+                    entry["quantizer"] = {"N": q.N, "E": q.E, "B1": q.B1, "B2": q.B2, "mu": q.mu, "alpha1": q.alpha1,
+                                          "A0": q.A0, "A1": q.A1, "percentile": 99.9}
                 del outs, cs
                 release()
             else:

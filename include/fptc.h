@@ -117,8 +117,10 @@ typedef struct {
   int32_t windows_per_chunk;  /* windows per decode work item (chunk); default 32 */
   int32_t waves_per_block;    /* 0: default (4; fptc_decode_batch: the most, up to 16, whose
                                  LDS fits; fptc_decompress_batch: the same, up to 8 at
-                                 N >= 128); at most 16 (fused: 8 at N >= 128, else
-                                 FPTC_ERR_UNSUPPORTED) */
+                                 N = 128); at most 16 (fused: 8 at N = 128, else
+                                 FPTC_ERR_UNSUPPORTED).  N = 256 (both MFMA calls): the
+                                 kernels always run 8 waves (0 or 8, else
+                                 FPTC_ERR_UNSUPPORTED for the fused call) */
   int32_t blocks;             /* persistent grid size; default: enough to fill the GPU */
   int32_t chunk_group;        /* fptc_decompress_batch at N <= 128: adjacent chunks per group, groups
                                  dealt round-robin over the grid (group g to block g mod blocks);
@@ -217,6 +219,49 @@ FPTC_API int32_t fptc_decompress_batch(const fptc_batch *batch, const fptc_codec
                                        const void *ws, size_t ws_bytes, const float *gamma, int32_t precision,
                                        float *out, int32_t *stream_status, void *stream);
 
+/* ------------------------------------------------ encode side (device calls)
+ * The steps before the decode path: the encoder's transform and quantizer,
+ * and the statistics a codebook and the paper quantizer are trained on.
+ * For these calls the batch supplies n_streams, n_samples, n_symbols,
+ * sample_off and book_id only (words may be NULL with n_words = 0). */
+
+/* Transform and quantize (Section 3.1, Section 3.2): every stream's samples x
+ * (device f32 [n_samples], CSR by batch->sample_off) cut into ceil(L/N)
+ * windows (the last zero-padded), each transformed by the orthonormal DCT-II
+ * X[k] = a_k * sum over n of x[n] cos(pi/N (n + 1/2) k) in FP64 (products and
+ * sums rounded separately, n ascending), its first E coefficients quantized
+ * by q: symbols_out (device u8 [n_symbols]) at sym_off[s], window-major.
+ * dct_table: device FP64 [E][N + 1] from fptc_build_dct_table.  sym_off:
+ * device [n_streams + 1], E times the exclusive prefix of ceil(L_s / N);
+ * n_symbols = sym_off[n_streams].  coef_out (device FP64 [n_symbols] or
+ * NULL) receives the coefficients X. */
+FPTC_API int32_t fptc_quantize_batch(const fptc_batch *batch, const fptc_quant_params *q, const double *dct_table,
+                                     const int64_t *sym_off, const float *x, uint8_t *symbols_out, double *coef_out,
+                                     void *stream);
+
+/* Symbol histogram per codebook (Section 3.3): adds the number of times each
+ * byte value occurs among stream s's symbols (device [n_symbols], at
+ * sym_off[s]) to counts[book_id[s]][value] (device u64 [n_books][256]; book 0
+ * when book_id is NULL; streams of books >= n_books are skipped).  The caller
+ * zeroes counts before the first call; exact integer counts. */
+FPTC_API int32_t fptc_histogram_batch(const fptc_batch *batch, const int64_t *sym_off, const uint8_t *symbols,
+                                      int32_t n_books, uint64_t *counts, void *stream);
+
+/* Bytes of device workspace fptc_abs_percentile needs. */
+FPTC_API size_t fptc_percentile_workspace_size(void);
+
+/* Clipped zone maximum (Section 3.2; Table 1's percentile): the p-th
+ * percentile, 0 <= p <= 100, of |coef[w][k]| over windows w < n_windows and
+ * bins k0 <= k < k1 of coef (device FP64 [n_windows][E]), with linear
+ * interpolation between order statistics: sorted values a, h = (M - 1) p/100,
+ * result a[floor h] + (a[floor h + 1] - a[floor h]) (h - floor h) (taken from
+ * the upper neighbour when that weight is at least 1/2).  The two order
+ * statistics are found exactly by radix selection on the FP64 bit patterns.
+ * out: device FP64 [1].  ws: device workspace, ws_bytes >=
+ * fptc_percentile_workspace_size(); calls sharing ws must not overlap. */
+FPTC_API int32_t fptc_abs_percentile(const double *coef, int64_t n_windows, int32_t E, int32_t k0, int32_t k1,
+                                     double p, double *out, void *ws, size_t ws_bytes, void *stream);
+
 /* ------------------------------------------------------------ host calls */
 
 /* Decode lookup table of one codebook (Section 3.3: 2^lmax entries indexed by
@@ -231,6 +276,11 @@ FPTC_API int32_t fptc_canonical_codes(const uint8_t *code_len, uint32_t *codes_o
 /* Length-limited optimal code lengths by package-merge (Section 3.3) from a
  * 256-entry histogram (host); symbols with count 0 get no code. */
 FPTC_API int32_t fptc_code_lengths(const uint64_t *freq, int32_t lmax, uint8_t *len_out);
+
+/* Forward transform table for fptc_quantize_batch (host FP64 [E][N + 1]):
+ * row k holds cos(pi/N (n + 1/2) k) for n < N, then a_k = sqrt(1/N) (k = 0)
+ * or sqrt(2/N) in column N (Section 3.1, orthonormal scaling). */
+FPTC_API int32_t fptc_build_dct_table(int32_t N, int32_t E, double *table_out);
 
 /* Orthonormal IDCT basis B[k][n] = a_k cos(pi/N (n + 1/2) k), a_0 = sqrt(1/N),
  * a_k = sqrt(2/N), for k < E, n < N, rounded to float (host [E][N]). */

@@ -71,7 +71,11 @@ def search_space(codec, fused, n_cu):
     space = []
     if fused and codec.N <= 128:
         space.append(("chunk_group", [0, 1, 2, 8, 16]))
-    space.append(("waves_per_block", [0, 12, 8] if codec.N <= 64 else [0, 4]))
+    if codec.N <= 64:
+        space.append(("waves_per_block", [0, 12, 8]))
+    elif codec.N == 128:
+        space.append(("waves_per_block", [0, 4]))
+    # window 256: one wave per (parity, column tile), always 8
     space.append(("windows_per_chunk", [0, 64, 16]))
     space.append(("blocks", [0, 2 * n_cu]))
     return space

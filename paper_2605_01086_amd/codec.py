@@ -184,3 +184,33 @@ def encode_batch(signals, book_id, q: F.fptc_quant_params, code_lens: np.ndarray
     idx = np.concatenate([np.arange(cap_off[i], cap_off[i] + nw[i]) for i in range(len(signals))]) \
         if len(signals) else np.zeros(0, np.int64)
     return words[idx], symlen[idx], word_off, sample_off
+
+
+# ---------------------------------------------------------------- device-side training steps
+
+
+def zone_maxima(train: np.ndarray, q: F.fptc_quant_params, percentile: float = 99.9, device="cuda"):
+    """A0 and A1 of the paper quantizer from a training strip, on the GPU: the
+    FP64 forward transform of its windows (fptc_quantize_batch) and the
+    percentile of |c| over the bins of zone 0 ([0, B1)) and zone 1 ([B1, B2))
+    (fptc_abs_percentile); an empty zone gives 1."""
+    train = np.ascontiguousarray(train, dtype=np.float32)
+    dev = torch.device(device)
+    L = int(train.shape[0])
+    nw = int(n_windows(np.array([L]), q.N)[0])
+    so = to_device(np.array([0, L], dtype=np.int64), dev)
+    yo = to_device(np.array([0, nw * q.E], dtype=np.int64), dev)
+    x = to_device(train, dev)
+    b = F.fptc_batch(1, 0, 0, nw * q.E, L, None, None, None, so.data_ptr(), None)
+    tab = to_device(F.fptc_build_dct_table(q.N, q.E), dev)
+    sym = torch.empty(max(1, nw * q.E), dtype=torch.uint8, device=dev)
+    coef = torch.empty(max(1, nw * q.E), dtype=torch.float64, device=dev)
+    F.fptc_quantize_batch(b, q, tab, yo, x, sym, coef)
+    ws = torch.empty(F.fptc_percentile_workspace_size(), dtype=torch.uint8, device=dev)
+    out = torch.ones(2, dtype=torch.float64, device=dev)
+    if q.B1 > 0:
+        F.fptc_abs_percentile(coef, nw, q.E, 0, q.B1, percentile, out[0:1], ws)
+    if q.B2 > q.B1:
+        F.fptc_abs_percentile(coef, nw, q.E, q.B1, q.B2, percentile, out[1:2], ws)
+    a = out.cpu().numpy()
+    return float(a[0]), float(a[1])

@@ -79,8 +79,6 @@ Layout layout_for(const fptc_batch *b, const fptc_codec *c, const Shape &s) {
   off = align256(off + L.tile_cap * sizeof(int32_t));
   L.chunk_meta = off;
   off = align256(off + L.chunk_cap * sizeof(ChunkMeta));
-  L.basis_split = off;
-  off = align256(off + basis_split256_bytes(c->N));
   L.total = off;
   return L;
 }
@@ -98,7 +96,6 @@ Plan plan_view(void *ws, const Layout &L) {
   v.seg_stream = reinterpret_cast<int32_t *>(p + L.seg_stream);
   v.seg_sum = reinterpret_cast<int32_t *>(p + L.seg_sum);
   v.seg_base = reinterpret_cast<int64_t *>(p + L.seg_base);
-  v.basis_split = reinterpret_cast<uint16_t *>(p + L.basis_split);
   v.chunk_cap = L.chunk_cap;
   v.tile_cap = L.tile_cap;
   v.seg_cap = L.seg_cap;
@@ -119,6 +116,37 @@ int device_cu_count() {
     cache[dev] = cu;
   }
   return cache[dev];
+}
+
+int check_decompress(const fptc_batch *batch, const fptc_codec *codec, const fptc_launch *launch, int32_t precision,
+                     const float *out, Shape *s) {
+  int rc;
+  if ((rc = check_batch(batch)) || (rc = check_codec(codec)) || (rc = resolve_shape(launch, codec, s))) return rc;
+  if (!out && batch->n_samples > 0) return FPTC_ERR_INVALID_ARG;
+  if (precision < FPTC_FP32_SIMT || precision > FPTC_BF16X3) return FPTC_ERR_INVALID_ARG;
+  const bool wide = codec->N == 256;
+  auto fits = [&](int waves) {
+    return wide ? fused256_supported(*codec, precision, s->wpc, waves)
+                : fused_supported(codec->N, codec->E, precision, s->wpc, waves, codec->n_books, codec->n_rows,
+                                  codec->lmax);
+  };
+  if (s->auto_waves) {  // the most waves (up to 16; 8 at N = 128 and 256) whose LDS fits
+    s->waves = wide ? 8 : 16;
+    while (s->waves > 1 && !fits(s->waves)) --s->waves;
+  }
+  if (!fits(s->waves)) return FPTC_ERR_UNSUPPORTED;
+  return FPTC_OK;
+}
+
+int launch_decompress(const fptc_batch &b, const fptc_codec &c, const Shape &s, const Plan &p, const float *gamma,
+                      int32_t precision, float *out, int32_t *stream_status, void *stream) {
+  if (c.N == 256) return status_of(launch_fused256(b, c, s, p, gamma, precision, out, stream_status, stream));
+  return status_of(launch_fused(b, c, s, p, gamma, precision, out, stream_status, stream));
+}
+
+int launch_plan_status(const fptc_batch &b, const fptc_codec &c, const Shape &s, const Plan &p, int32_t *status,
+                       void *stream) {
+  return status_of(launch_plan(b, c, s, p, status, stream));
 }
 
 }  // namespace fptc
@@ -176,7 +204,8 @@ int32_t fptc_dequant_idct(const fptc_batch *batch, const fptc_codec *codec, cons
   if (precision < FPTC_FP32_SIMT || precision > FPTC_BF16X3) return FPTC_ERR_INVALID_ARG;
   const bool wide = codec->N == 256;
   if (precision != FPTC_FP32_SIMT &&
-      !(wide ? mfma256_supported(codec->E, precision) : mfma_supported(codec->N, codec->E, precision, codec->n_books, codec->n_rows)))
+      !(wide ? mfma256_supported(*codec, precision, s.wpc)
+             : mfma_supported(codec->N, codec->E, precision, codec->n_books, codec->n_rows)))
     return FPTC_ERR_UNSUPPORTED;
   Layout L = layout_for(batch, codec, s);
   if (ws_bytes < L.total) return FPTC_ERR_WORKSPACE;
@@ -208,26 +237,48 @@ int32_t fptc_decompress_batch(const fptc_batch *batch, const fptc_codec *codec, 
                               int32_t *stream_status, void *stream) {
   Shape s;
   int rc;
-  if ((rc = check_batch(batch)) || (rc = check_codec(codec)) || (rc = resolve_shape(launch, codec, &s))) return rc;
-  if (!ws || (!out && batch->n_samples > 0)) return FPTC_ERR_INVALID_ARG;
-  if (precision < FPTC_FP32_SIMT || precision > FPTC_BF16X3) return FPTC_ERR_INVALID_ARG;
-  const bool wide = codec->N == 256;
-  auto fits = [&](int waves) {
-    return wide ? fused256_supported(*codec, precision, s.wpc, waves)
-                : fused_supported(codec->N, codec->E, precision, s.wpc, waves, codec->n_books, codec->n_rows,
-                                  codec->lmax);
-  };
-  if (s.auto_waves) {  // the most waves (up to 16; 8 at N = 128 and 256) whose LDS fits
-    s.waves = wide ? 8 : 16;
-    while (s.waves > 1 && !fits(s.waves)) --s.waves;
-  }
-  if (!fits(s.waves)) return FPTC_ERR_UNSUPPORTED;
+  if ((rc = check_decompress(batch, codec, launch, precision, out, &s))) return rc;
+  if (!ws) return FPTC_ERR_INVALID_ARG;
   Layout L = layout_for(batch, codec, s);
   if (ws_bytes < L.total) return FPTC_ERR_WORKSPACE;
   if (ensure_device_init()) return FPTC_ERR_HIP;
-  Plan pv = plan_view(const_cast<void *>(ws), L);
-  if (wide) return status_of(launch_fused256(*batch, *codec, s, pv, gamma, precision, out, stream_status, stream));
-  return status_of(launch_fused(*batch, *codec, s, pv, gamma, precision, out, stream_status, stream));
+  return launch_decompress(*batch, *codec, s, plan_view(const_cast<void *>(ws), L), gamma, precision, out,
+                           stream_status, stream);
+}
+
+int32_t fptc_quantize_batch(const fptc_batch *batch, const fptc_quant_params *q, const double *dct_table,
+                            const int64_t *sym_off, const float *x, uint8_t *symbols_out, double *coef_out,
+                            void *stream) {
+  if (!batch || batch->n_streams < 1 || batch->n_samples < 0 || batch->n_symbols < 0 || !batch->sample_off)
+    return FPTC_ERR_INVALID_ARG;
+  if (check_quant_params(q)) return FPTC_ERR_INVALID_ARG;
+  if (!dct_table || !sym_off || (!x && batch->n_samples > 0) || (!symbols_out && batch->n_symbols > 0))
+    return FPTC_ERR_INVALID_ARG;
+  if (batch->n_symbols % q->E) return FPTC_ERR_INVALID_ARG;
+  if (batch->n_symbols == 0) return FPTC_OK;
+  if (ensure_device_init()) return FPTC_ERR_HIP;
+  return status_of(launch_fdct_quant(*batch, *q, dct_table, sym_off, x, symbols_out, coef_out,
+                                     batch->n_symbols / q->E, stream));
+}
+
+int32_t fptc_histogram_batch(const fptc_batch *batch, const int64_t *sym_off, const uint8_t *symbols, int32_t n_books,
+                             uint64_t *counts, void *stream) {
+  if (!batch || batch->n_streams < 1 || batch->n_symbols < 0 || !sym_off || !counts) return FPTC_ERR_INVALID_ARG;
+  if (n_books < 1 || n_books > kMaxBooks || (!symbols && batch->n_symbols > 0)) return FPTC_ERR_INVALID_ARG;
+  if (batch->n_symbols == 0) return FPTC_OK;
+  if (ensure_device_init()) return FPTC_ERR_HIP;
+  return status_of(launch_histogram(*batch, sym_off, n_books, symbols, counts, batch->n_symbols, stream));
+}
+
+size_t fptc_percentile_workspace_size(void) { return percentile_ws_bytes(); }
+
+int32_t fptc_abs_percentile(const double *coef, int64_t n_windows, int32_t E, int32_t k0, int32_t k1, double p,
+                            double *out, void *ws, size_t ws_bytes, void *stream) {
+  if (!coef || !out || !ws || n_windows < 1 || E < 1 || k0 < 0 || k1 <= k0 || k1 > E) return FPTC_ERR_INVALID_ARG;
+  if (!(p >= 0.0 && p <= 100.0)) return FPTC_ERR_INVALID_ARG;
+  if (ws_bytes < percentile_ws_bytes()) return FPTC_ERR_WORKSPACE;
+  if (ensure_device_init()) return FPTC_ERR_HIP;
+  return status_of(launch_abs_percentile(coef, n_windows, E, k0, k1, p / 100.0, out, ws, stream));
 }
 
 }  // extern "C"

@@ -164,16 +164,19 @@ __device__ inline void stage_decode_tables(bool ms, unsigned char *lut, unsigned
   __syncthreads();
 }
 
-// The words of a chunk's first kPreRounds rounds, one per lane per round.
-struct ChunkWords {
-  uint64_t w[kPreRounds];
-  int n[kPreRounds];
+// The words of a chunk's first PR rounds, one per lane per round.
+template <int PR = kPreRounds>
+struct ChunkWordsT {
+  uint64_t w[PR];
+  int n[PR];
 };
+using ChunkWords = ChunkWordsT<kPreRounds>;
 
+template <int PR>
 __device__ inline void load_chunk_words(const uint64_t *__restrict__ words, const uint8_t *__restrict__ symlen,
-                                        int64_t fw, int64_t wend, int lane, ChunkWords &cw) {
+                                        int64_t fw, int64_t wend, int lane, ChunkWordsT<PR> &cw) {
 #pragma unroll
-  for (int r = 0; r < kPreRounds; ++r) {
+  for (int r = 0; r < PR; ++r) {
     const int64_t w = fw + 64 * r + lane;
     cw.w[r] = 0;
     cw.n[r] = 0;
@@ -188,9 +191,10 @@ __device__ inline void load_chunk_words(const uint64_t *__restrict__ words, cons
 // asm statement that reads them makes the compiler place its wait for their
 // loads here rather than at the loop's back edge, where it would also wait
 // for every store issued in between.
-__device__ inline void settle_chunk_words(const ChunkWords &cw) {
+template <int PR>
+__device__ inline void settle_chunk_words(const ChunkWordsT<PR> &cw) {
 #pragma unroll
-  for (int r = 0; r < kPreRounds; ++r) asm volatile("" ::"v"(cw.w[r]), "v"(cw.n[r]) : "memory");
+  for (int r = 0; r < PR; ++r) asm volatile("" ::"v"(cw.w[r]), "v"(cw.n[r]) : "memory");
 }
 
 // Decode cnt > 0 symbols of one word into p[0 .. cnt); p may start up to 63
@@ -326,18 +330,18 @@ __device__ inline void decode_round(uint64_t word, int n, int &P, int t_cnt, con
 // Decode symbols [0, t_cnt) of a chunk into sb[0 .. t_cnt), one wavefront.
 // fw is the first word holding a symbol of the chunk, p0 <= 0 the chunk-
 // relative index of that word's first symbol, wend the stream's word end;
-// cw holds the first kPreRounds rounds of words (load_chunk_words), later
+// cw holds the first PR rounds of words (load_chunk_words), later
 // rounds are loaded here one round ahead.  binfo: the codebook's info word
 // (multi-symbol tables; 0 otherwise).  Returns this lane's error bits.
-template <bool MS>
+template <bool MS, int PR>
 __device__ inline int decode_chunk(const uint64_t *__restrict__ words, const uint8_t *__restrict__ symlen, int64_t fw,
-                                   int p0, int t_cnt, int64_t wend, const ChunkWords &cw, const void *lut,
+                                   int p0, int t_cnt, int64_t wend, const ChunkWordsT<PR> &cw, const void *lut,
                                    const uint8_t *cl, uint32_t binfo, int hs, unsigned char *sb, int lane) {
   int err = 0, P = p0;
   if (MS && (binfo & 1u)) prefill_symbols(sb, t_cnt, (binfo >> 8) & 255u, lane);
   int64_t w = fw;
 #pragma unroll
-  for (int r = 0; r < kPreRounds; ++r) {
+  for (int r = 0; r < PR; ++r) {
     if (P < t_cnt && w < wend) decode_round<MS>(cw.w[r], cw.n[r], P, t_cnt, lut, cl, binfo, hs, sb, err);
     w += 64;
   }

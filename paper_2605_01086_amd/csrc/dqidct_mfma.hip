@@ -35,15 +35,10 @@ constexpr int kWaves = kThreads / 64;
 
 __host__ __device__ constexpr size_t a16(size_t x) { return (x + 15) & ~(size_t)15; }
 
-__host__ __device__ constexpr size_t table_bytes(int bpieces, int n_books, int n_rows, int E) {
-  return a16((size_t)n_books * n_rows * 256 * 5 + (size_t)n_books * E) +
-         (bpieces <= 2 ? a16((size_t)n_books * n_rows * 256 * 4) : 0);
-}
-
 // LDS bytes of one instantiation: basis pieces, tables, one 32-window symbol
 // tile per wave, the chunk counter (16 B).
 __host__ __device__ constexpr size_t mfma_lds_bytes(int bpieces, int N, int Kp, int n_books, int n_rows, int E) {
-  return (size_t)bpieces * N * (Kp + 8) * 2 + table_bytes(bpieces, n_books, n_rows, E) +
+  return (size_t)bpieces * N * (Kp + 8) * 2 + deq_table_bytes(bpieces, n_books, n_rows, E) +
          (size_t)kWaves * (16 + a16((size_t)kTileWindows * E + 16)) + 16;
 }
 
@@ -114,26 +109,14 @@ __global__ void __launch_bounds__(kThreads, NT >= 4 ? 2 : (NT == 2 ? 3 : 4)) k_d
   constexpr int BP = T::kBPieces, AP = T::kAPieces;
   extern __shared__ __align__(16) unsigned char lds[];
   uint16_t *Bs = reinterpret_cast<uint16_t *>(lds);                       // [BP][N][RS]
-  float *Tv = reinterpret_cast<float *>(lds + (size_t)BP * N * RS * 2);    // [books][rows][256]
-  uint8_t *Tz = reinterpret_cast<uint8_t *>(Tv + n_books * n_rows * 256);  // [books][rows][256]
-  uint8_t *Rb = Tz + n_books * n_rows * 256;                               // [books][E]
-  uint32_t *Pq = reinterpret_cast<uint32_t *>(reinterpret_cast<unsigned char *>(Tv) +
-                                              a16((size_t)n_books * n_rows * 256 * 5 + (size_t)n_books * E));
-  unsigned char *bufs = reinterpret_cast<unsigned char *>(Tv) + table_bytes(BP, n_books, n_rows, E);
+  unsigned char *tables = lds + (size_t)BP * N * RS * 2;
+  const DeqTables dt = deq_tables_at(tables, n_books, n_rows, E);
+  unsigned char *bufs = tables + deq_table_bytes(AP, n_books, n_rows, E);
 
   // Stage the split basis (transposed to [n][k], zero beyond E) and the tables.
   const float bscale = T::kF16 ? kBasisScaleF16 : 1.0f;
   stage_basis<PREC>(Bs, basis, N, E, Kp, RS, threadIdx.x, kThreads);
-  for (int i = threadIdx.x; i < n_books * n_rows * 256; i += kThreads) {
-    Tv[i] = deq_val[i];
-    const int z = deq_zone[i];
-    Tz[i] = (uint8_t)(z < 2 ? z : 2);
-  }
-  for (int i = threadIdx.x; i < n_books * E; i += kThreads) {
-    const int r = row_of_bin[i];
-    Rb[i] = (uint8_t)(r < n_rows ? r : n_rows - 1);
-  }
-  if constexpr (AP <= 2) stage_pieces<PREC>(Pq, deq_val, n_books * n_rows * 256, threadIdx.x, kThreads);
+  stage_deq_tables<PREC>(dt, deq_val, deq_zone, row_of_bin, n_books, n_rows, E, threadIdx.x, kThreads);
   unsigned *chunk_ctr = reinterpret_cast<unsigned *>(bufs + (size_t)kWaves * (16 + a16((size_t)kTileWindows * E + 16)));
   if (threadIdx.x == 0) *chunk_ctr = 0;
   __syncthreads();
@@ -164,7 +147,8 @@ __global__ void __launch_bounds__(kThreads, NT >= 4 ? 2 : (NT == 2 ? 3 : 4)) k_d
   while (c < n_chunks) {
     const int book = cm.book < n_books && cm.book >= 0 ? cm.book : 0;
     const int w_cnt = cm.n_windows;
-    const float g0 = lane_float(vg, 0), g1 = lane_float(vg, 1), g2 = lane_float(vg, 2);
+    const ChunkScales cs = chunk_scales<PREC>(gamma, lane_float(vg, 0), lane_float(vg, 1), lane_float(vg, 2),
+                                              dt.vmax[book], oscale);
     const int64_t cmm = sched.next(lane);
     const uint32_t vm = load_meta_lane(meta, cmm, n_chunks, lane);
     const float vgn = load_gamma_lane(gamma, stream_of(nm), lane);
@@ -194,17 +178,17 @@ __global__ void __launch_bounds__(kThreads, NT >= 4 ? 2 : (NT == 2 ? 3 : 4)) k_d
         }
         if (E == N) {  // stage through the consumed symbol tile
           if (rem >= kTileWindows * N)
-            store_tile_whole<NT>(win0, acc, reinterpret_cast<float *>(sb) - 4, h, col, lane, oscale);
+            store_tile_whole<NT>(win0, acc, reinterpret_cast<float *>(sb) - 4, h, col, lane, cs.out);
           else
-            store_tile_staged<NT>(win0, acc, reinterpret_cast<float *>(sb) - 4, h, col, lane, rem, oscale);
+            store_tile_staged<NT>(win0, acc, reinterpret_cast<float *>(sb) - 4, h, col, lane, rem, cs.out);
         } else {
 #pragma unroll
-          for (int t = 0; t < NT; ++t) store_rows(win0, N, acc[t], t, h, col, rem, oscale);
+          for (int t = 0; t < NT; ++t) store_rows(win0, N, acc[t], t, h, col, rem, cs.out);
         }
       };
-      tile_contract_emit<PREC, NT>(sb, base, h, col, S, E, valid > 0, Bs, RS, Rb + book * E,
-                                   Tv + book * n_rows * 256, Tz + book * n_rows * 256, Pq + book * n_rows * 256,
-                                   n_rows, gamma, g0, g1, g2, emit);
+      tile_contract_emit<PREC, NT>(sb, base, h, col, S, E, valid > 0, Bs, RS, dt.rb + book * E,
+                                   dt.tv + book * n_rows * 256, dt.tz + book * n_rows * 256,
+                                   dt.pq + book * n_rows * 256, n_rows, gamma, cs, emit);
       wave_sync_lds();
     }
     settle_tile_syms(nx);

@@ -55,8 +55,7 @@ struct Shape {
 //   tile_stream int32[tcap] stream owning the first window of each 32-window tile
 //   chunk_meta ChunkMeta[cap] per-chunk decode record
 struct Layout {
-  size_t hdr, win_off, chunk_off, seg_off, bwd_part, tile_stream, seg_stream, seg_sum, seg_base, chunk_meta,
-      basis_split, total;
+  size_t hdr, win_off, chunk_off, seg_off, bwd_part, tile_stream, seg_stream, seg_sum, seg_base, chunk_meta, total;
   int64_t chunk_cap, tile_cap, seg_cap;
 };
 
@@ -74,7 +73,6 @@ struct Plan {
   int32_t *seg_sum;     // [seg_cap] symbols in each segment
   int64_t *seg_base;    // [seg_cap] symbols of the stream before each segment
   ChunkMeta *chunk_meta;
-  uint16_t *basis_split;  // window 256: the split basis in the LDS image of each staged block
   int64_t chunk_cap, tile_cap, seg_cap;
 };
 
@@ -97,8 +95,7 @@ bool fused_supported(int N, int E, int precision, int wpc, int waves, int n_book
 int launch_fused(const fptc_batch &b, const fptc_codec &c, const Shape &s, const Plan &p, const float *gamma,
                  int precision, float *out, int32_t *status, void *stream);
 
-bool mfma256_supported(int E, int precision);
-size_t basis_split256_bytes(int N);
+bool mfma256_supported(const fptc_codec &c, int precision, int wpc);
 bool fused256_supported(const fptc_codec &c, int precision, int wpc, int waves);
 int launch_dqidct_mfma256(const fptc_batch &b, const fptc_codec &c, const Shape &s, const Plan &p,
                           const uint8_t *symbols, const float *gamma, int precision, float *out, void *stream);
@@ -111,6 +108,27 @@ int launch_bwd(const fptc_batch &b, const fptc_codec &c, const Shape &s, const P
 
 int device_cu_count();
 
+// Encode-side steps (train.hip).
+int launch_fdct_quant(const fptc_batch &b, const fptc_quant_params &q, const double *tab, const int64_t *sym_off,
+                      const float *x, uint8_t *symbols, double *coef, int64_t n_windows, void *stream);
+int launch_histogram(const fptc_batch &b, const int64_t *sym_off, int n_books, const uint8_t *symbols,
+                     uint64_t *counts, int64_t n_symbols, void *stream);
+size_t percentile_ws_bytes();
+int launch_abs_percentile(const double *coef, int64_t n_windows, int E, int k0, int k1, double q, double *out,
+                          void *ws, void *stream);
+int check_quant_params(const fptc_quant_params *q);  // host_tables.cpp
+
+// Host-side checks and launches of the ABI calls, shared by the entry points
+// (return fptc_status codes).  check_decompress resolves the launch shape of
+// fptc_decompress_batch (waves included) and validates every argument that
+// needs no workspace.
+int check_decompress(const fptc_batch *batch, const fptc_codec *codec, const fptc_launch *launch, int32_t precision,
+                     const float *out, Shape *s);
+int launch_decompress(const fptc_batch &b, const fptc_codec &c, const Shape &s, const Plan &p, const float *gamma,
+                      int32_t precision, float *out, int32_t *stream_status, void *stream);
+int launch_plan_status(const fptc_batch &b, const fptc_codec &c, const Shape &s, const Plan &p, int32_t *status,
+                       void *stream);
+
 // Library set-up on the current device, once per device (thread-safe):
 // kernel attributes (dynamic LDS up to 160 KB) for every kernel
 // instantiation.  Every device entry point runs it before enqueueing, so the
@@ -121,6 +139,7 @@ int set_dqidct_mfma_attributes();
 int set_fused_attributes();
 int set_mfma256_attributes();
 int set_bwd_attributes();
+int init_noalloc_scratch();  // the no-allocation entry point's static workspace
 
 #ifdef __HIPCC__
 // Allow a kernel the whole 160 KB of a CU's LDS as dynamic shared memory.

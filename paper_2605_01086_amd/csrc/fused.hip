@@ -36,20 +36,13 @@ __host__ __device__ inline size_t fused_wave_bytes(int E, int wpc) {
   return (size_t)kSymPrefix + align16((size_t)wpc * E + 16);
 }
 
-// Dequantization tables: values, zones, row of each bin and, for at most two
-// pieces, the pre-split values.
-__host__ __device__ inline size_t fused_table_bytes(int bpieces, int n_books, int n_rows, int E) {
-  return align16((size_t)n_books * n_rows * 256 * 5 + (size_t)n_books * E) +
-         (bpieces <= 2 ? align16((size_t)n_books * n_rows * 256 * 4) : 0);
-}
-
 // LDS: lookup tables | split basis | dequantization tables | wave buffers |
 // chunk counter (16 B).  The multi-symbol build borrows lut1_temp_bytes right
 // after the tables.
 __host__ __device__ inline size_t fused_lds_bytes(bool ms, int bpieces, int N, int E, int Kp, int wpc, int waves,
                                                   int n_books, int n_rows, int lmax) {
   const size_t t = lut_lds_bytes(ms, n_books, lmax);
-  const size_t need = t + (size_t)bpieces * N * (Kp + 8) * 2 + fused_table_bytes(bpieces, n_books, n_rows, E) +
+  const size_t need = t + (size_t)bpieces * N * (Kp + 8) * 2 + deq_table_bytes(bpieces, n_books, n_rows, E) +
                       (size_t)waves * fused_wave_bytes(E, wpc) + 16;
   const size_t tmp = ms ? t + lut1_temp_bytes(n_books, lmax) : 0;
   return need > tmp ? need : tmp;
@@ -76,26 +69,14 @@ __global__ void __launch_bounds__(64 * max_fused_waves(NT * 32)) k_fused(const u
   const int nthreads = blockDim.x, waves = nthreads >> 6;
   const size_t lut_bytes = lut_lds_bytes(MS, n_books, lmax);
   uint16_t *Bs = reinterpret_cast<uint16_t *>(lds + lut_bytes);
-  float *Tv = reinterpret_cast<float *>(Bs + (size_t)T::kBPieces * N * RS);
-  uint8_t *Tz = reinterpret_cast<uint8_t *>(Tv + n_books * n_rows * 256);
-  uint8_t *Rb = Tz + n_books * n_rows * 256;
-  uint32_t *Pq = reinterpret_cast<uint32_t *>(reinterpret_cast<unsigned char *>(Tv) +
-                                              align16((size_t)n_books * n_rows * 256 * 5 + (size_t)n_books * E));
-  unsigned char *wave_base = reinterpret_cast<unsigned char *>(Tv) + fused_table_bytes(AP, n_books, n_rows, E);
+  unsigned char *tables = reinterpret_cast<unsigned char *>(Bs + (size_t)T::kBPieces * N * RS);
+  const DeqTables dt = deq_tables_at(tables, n_books, n_rows, E);
+  unsigned char *wave_base = tables + deq_table_bytes(AP, n_books, n_rows, E);
 
   // ---- block setup: lookup tables, basis pieces, dequantization tables
   stage_decode_tables(MS, lds, lds + lut_bytes, lut_g, lmax, n_books, threadIdx.x, nthreads);
   stage_basis<PREC>(Bs, basis, N, E, Kp, RS, threadIdx.x, nthreads);
-  for (int i = threadIdx.x; i < n_books * n_rows * 256; i += nthreads) {
-    Tv[i] = deq_val[i];
-    const int z = deq_zone[i];
-    Tz[i] = (uint8_t)(z < 2 ? z : 2);
-  }
-  for (int i = threadIdx.x; i < n_books * E; i += nthreads) {
-    const int r = row_of_bin[i];
-    Rb[i] = (uint8_t)(r < n_rows ? r : n_rows - 1);
-  }
-  if constexpr (AP <= 2) stage_pieces<PREC>(Pq, deq_val, n_books * n_rows * 256, threadIdx.x, nthreads);
+  stage_deq_tables<PREC>(dt, deq_val, deq_zone, row_of_bin, n_books, n_rows, E, threadIdx.x, nthreads);
   unsigned *chunk_ctr = reinterpret_cast<unsigned *>(wave_base + (size_t)waves * fused_wave_bytes(E, wpc));
   if (threadIdx.x == 0) *chunk_ctr = 0;
   __syncthreads();
@@ -154,7 +135,8 @@ __global__ void __launch_bounds__(64 * max_fused_waves(NT * 32)) k_fused(const u
     cw = nx;
     if (ok) {
       if (err && status) atomicOr(&status[s], err);
-      const float g0 = lane_float(vg, 0), g1 = lane_float(vg, 1), g2 = lane_float(vg, 2);
+      const ChunkScales cs = chunk_scales<PREC>(gamma, lane_float(vg, 0), lane_float(vg, 1), lane_float(vg, 2),
+                                                dt.vmax[book], oscale);
       wave_sync_lds();
 
       // ---- 2. per 32 windows: dequantize, contract, store
@@ -169,17 +151,17 @@ __global__ void __launch_bounds__(64 * max_fused_waves(NT * 32)) k_fused(const u
         auto emit = [&](const f16v (&acc)[NT]) {
           if (E == N && wpc >= kTileWindows) {  // a quarter tile fits in the consumed symbol buffer
             if (rem >= kTileWindows * N)
-              store_tile_whole<NT>(win0, acc, reinterpret_cast<float *>(sb) - 4, h, col, lane, oscale);
+              store_tile_whole<NT>(win0, acc, reinterpret_cast<float *>(sb) - 4, h, col, lane, cs.out);
             else
-              store_tile_staged<NT>(win0, acc, reinterpret_cast<float *>(sb) - 4, h, col, lane, rem, oscale);
+              store_tile_staged<NT>(win0, acc, reinterpret_cast<float *>(sb) - 4, h, col, lane, rem, cs.out);
           } else {
 #pragma unroll
-            for (int t = 0; t < NT; ++t) store_rows(win0, N, acc[t], t, h, col, rem, oscale);
+            for (int t = 0; t < NT; ++t) store_rows(win0, N, acc[t], t, h, col, rem, cs.out);
           }
         };
-        tile_contract_emit<PREC, NT>(sb, base, h, col, S, E, valid > 0, Bs, RS, Rb + book * E,
-                                     Tv + book * n_rows * 256, Tz + book * n_rows * 256, Pq + book * n_rows * 256,
-                                     n_rows, gamma, g0, g1, g2, emit);
+        tile_contract_emit<PREC, NT>(sb, base, h, col, S, E, valid > 0, Bs, RS, dt.rb + book * E,
+                                     dt.tv + book * n_rows * 256, dt.tz + book * n_rows * 256,
+                                     dt.pq + book * n_rows * 256, n_rows, gamma, cs, emit);
       }
       wave_sync_lds();
     }

@@ -102,6 +102,12 @@ int check_quant(const fptc_quant_params *q) {
   return FPTC_ERR_INVALID_ARG;
 }
 
+}  // namespace
+
+int fptc::check_quant_params(const fptc_quant_params *q) { return check_quant(q); }
+
+namespace {
+
 // Orthonormal DCT-II basis in double: B[k][n] = a_k cos(pi/N (n + 1/2) k).
 std::vector<double> basis64(int N, int E) {
   std::vector<double> B((size_t)E * N);
@@ -279,6 +285,16 @@ int32_t fptc_code_lengths(const uint64_t *freq, int32_t lmax, uint8_t *len_out) 
   for (int i = 0; i < 2 * n - 2; ++i)
     for (int j = 0; j < n; ++j) tot[j] += cur[i].cnt[j];
   for (int j = 0; j < n; ++j) len_out[used[j]] = (uint8_t)tot[j];
+  return FPTC_OK;
+}
+
+int32_t fptc_build_dct_table(int32_t N, int32_t E, double *table_out) {
+  if (!table_out || !valid_n(N) || E < 1 || E > N) return FPTC_ERR_INVALID_ARG;
+  for (int k = 0; k < E; ++k) {
+    double *row = table_out + (size_t)k * (N + 1);
+    for (int n = 0; n < N; ++n) row[n] = std::cos(kPi / N * (n + 0.5) * k);
+    row[N] = k == 0 ? std::sqrt(1.0 / N) : std::sqrt(2.0 / N);
+  }
   return FPTC_OK;
 }
 

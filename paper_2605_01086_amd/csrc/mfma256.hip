@@ -1,12 +1,31 @@
-// Window 256 on the matrix cores: the split IDCT basis (256 x 256 in two or
-// three 16-bit pieces) does not fit in LDS, so a workgroup stages it 64 bins
-// at a time and every wave's 32-window tile accumulates over the staged
-// blocks.  Same operand splitting, bin-to-k-slot map and accumulation order
-// (k-steps from the highest bins down) as the resident kernels.
+// Window 256 on the matrix cores (Section 4.2 lossy stage, Eq. 1 inverted).
 //
-// Both kernels keep their loops uniform across the workgroup: every wave
-// reaches every barrier, with idle waves (no chunk or tile) skipping only the
-// arithmetic.
+// The inverse DCT rows obey B[k][N-1-n] = (-1)^k B[k][n].  With
+//     E[w][n] = sum over even bins k of c[w][k] B[k][n],
+//     O[w][n] = sum over odd bins  k of c[w][k] B[k][n],      n < 128,
+// the samples are x[w][n] = E + O and x[w][255 - n] = E - O: two 128 x 128
+// contractions instead of one 256 x 256, half the matrix-core work and half
+// the basis.
+//
+// A workgroup has 8 waves.  Wave w owns parity p = w / 4 (even or odd bins)
+// and the 32 output columns n = 32 (w % 4) + lane % 32 of the half; its slice
+// of the split basis (up to 8 k-steps x the precision's 16-bit pieces) is
+// loaded into registers once and never restaged.  Work comes in rounds of 8
+// chunks (runs of up to wpc windows of one stream, from the plan):
+//   1. each wave puts one chunk's symbols into its LDS buffer: the fused
+//      kernel decodes them from the words (the same per-chunk decode as the
+//      other fused kernel), the split kernel copies them from the symbol
+//      array;
+//   2. for every 32-window tile of the round's chunks, each wave contracts its
+//      parity's dequantized coefficients of the tile's windows with its basis
+//      slice on v_mfma_f32_32x32x16 (coefficients as the A operand), the even
+//      and odd waves of a column tile swap their partial sums through LDS,
+//      and the even wave writes x[n] = E + O, the odd wave x[255 - n] = E - O:
+//      each store instruction writes 32 consecutive samples of two windows.
+// Both kernels run the same contraction code, so their outputs are
+// bit-identical.  The words of the next round are requested before the
+// contraction and waited for before its first store; vector memory counters
+// retire in order, so a later wait would also wait for the stores.
 #include <hip/hip_runtime.h>
 
 #include "decode_common.h"
@@ -16,398 +35,414 @@
 namespace fptc {
 namespace {
 
-constexpr int N256 = 256, NT256 = 8;
-constexpr int kSB = 4;                 // k-steps per staged block (64 bins)
-constexpr int kRSB = 16 * kSB + 8;     // LDS row stride of a staged block, in halves
-constexpr int kMaxWaves256 = 8;
+constexpr int N256 = 256;
+constexpr int kWaves256 = 8;
+constexpr int kMaxSteps = 8;      // k-steps of 16 bins of one parity (128 bins)
+constexpr int kPre256 = 8;        // rounds of 64 words requested a round ahead (512 words)
+constexpr int kSymVec = 8;        // 16-byte symbol vectors per lane requested a round ahead (8 KB)
+constexpr int kXchBytes = 64 * 16 * 4;  // one wave's 32 x 32 partial sums
 
 __host__ __device__ constexpr size_t a16(size_t x) { return (x + 15) & ~(size_t)15; }
 
-__host__ __device__ inline size_t block_basis_bytes(int bpieces) { return (size_t)bpieces * N256 * kRSB * 2; }
+// Per-wave symbol buffer: a prefix for symbols of the word before the chunk
+// (decode), the chunk's symbols, and 256 bytes of slack: the contraction reads
+// 256 bytes from the start of every window whatever E is.
+__host__ __device__ inline size_t wave256_bytes(int wpc, int E) { return (size_t)kSymPrefix + a16((size_t)wpc * E + 256); }
 
-// Stage k-steps [s0, s0 + kSB) of the split basis: for lane half h the bins
-// h*KH + 8 s + j, stored at row n, column h*8*kSB + 8 (s - s0) + j.
-template <int PREC>
-__device__ inline void stage_basis_block(uint16_t *Bb, const float *basis, int E, int KH, int s0, int tid,
-                                         int nthreads) {
-  using T = Traits<PREC>;
-  constexpr int BP = T::kBPieces;
-  const float bscale = T::kF16 ? kBasisScaleF16 : 1.0f;
-  constexpr int W = 16 * kSB;
-  for (int i = tid; i < N256 * W; i += nthreads) {
-    const int n = i % N256, r = i / N256;  // consecutive threads read consecutive n of one basis row
-    const int h = r / (8 * kSB), o = r % (8 * kSB);
-    const int k = h * KH + 8 * s0 + o;
-    const float v = k < E ? basis[(int64_t)k * N256 + n] * bscale : 0.0f;
-    uint16_t pc[BP];
-    split<T::kF16, BP>(v, pc);
-#pragma unroll
-    for (int p = 0; p < BP; ++p) Bb[(p * N256 + n) * kRSB + r] = pc[p];
-  }
-}
+// What every wave needs of each chunk of the round, written by its owner.
+struct Slot {
+  int64_t out_base;  // first output sample
+  int32_t out_len;   // samples of the chunk
+  int32_t n_win;     // windows (0: nothing to do)
+  int32_t book;
+  int32_t scaled;
+  float g0, g1, g2, oscale;  // coefficient factors per zone, output factor (ChunkScales)
+  int32_t pad[2];
+};
+static_assert(sizeof(Slot) == 48, "slot size");
 
-constexpr int kMaxBlocks256 = (N256 / 16 + kSB - 1) / kSB;  // staged blocks at E = 256
-
-// The split basis of every staged block, written once per call into the
-// workspace in the exact LDS image of the block, so that staging a block in
-// the main kernels is a plain 16-byte copy.  One workgroup per block.
-template <int PREC>
-__global__ void __launch_bounds__(256) k_split_basis256(const float *__restrict__ basis, int E, int KH,
-                                                        uint16_t *bsplit) {
-  using T = Traits<PREC>;
-  const int blk = blockIdx.x;
-  stage_basis_block<PREC>(bsplit + (size_t)blk * (block_basis_bytes(T::kBPieces) / 2), basis, E, KH, blk * kSB,
-                          threadIdx.x, blockDim.x);
-}
-
-// Copy one staged block (bytes a multiple of 16) from the workspace to LDS.
-__device__ inline void copy_basis_block(uint16_t *Bb, const uint16_t *__restrict__ src, int bytes, int tid,
-                                        int nthreads) {
-  const uint4 *s4 = reinterpret_cast<const uint4 *>(src);
-  uint4 *d4 = reinterpret_cast<uint4 *>(Bb);
-  for (int i = tid; i < bytes / 16; i += nthreads) d4[i] = s4[i];
-}
-
-// Contract k-steps [s0, s1) of one 32-window tile against the staged block;
-// symbols come from `sym(k0)`: the 8 symbols of bins k0 .. k0 + 7, byte j of
-// the pair being bin k0 + j.  (The pre-split table of the resident kernels
-// is not used here: with eight 32-row output tiles the accumulators already
-// take half of the 256 registers a wave has at eight waves per block.)
-template <int PREC, typename SymFn>
-__device__ inline void contract_block256(f16v (&acc)[NT256], const uint16_t *Bb, int s0, int s1, int KH, int h,
-                                         int col, int E, bool valid, const uint8_t *rb, const float *tv,
-                                         const uint8_t *tz, bool scaled, float g0, float g1, float g2, SymFn sym) {
-  using T = Traits<PREC>;
-  constexpr int AP = T::kAPieces;
-#pragma unroll 1
-  for (int s = s1 - 1; s >= s0; --s) {
-    const int k0 = h * KH + 8 * s;
-    const uint2 u = sym(k0);
-    uint8_t sy[8];
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      sy[j] = (uint8_t)(u.x >> (8 * j));
-      sy[4 + j] = (uint8_t)(u.y >> (8 * j));
-    }
-    u8v a[AP];
-    const bool r = dequant8<PREC>(sy, k0, E, valid, rb, tv, tz, scaled, g0, g1, g2, a);
-    const bool any_rest = AP > 1 && __any(r);
-    mfma_step<PREC, NT256>(acc, a, Bb + col * kRSB + h * 8 * kSB + 8 * (s - s0), 32 * kRSB, N256 * kRSB, any_rest);
-  }
-}
-
-// ---------------------------------------------------------------- split path
-template <int PREC>
-__global__ void __launch_bounds__(kMaxWaves256 * 64) k_dqidct_mfma256(fptc_batch b, int E, int S, int n_books,
-                                                                       int n_rows, const float *deq_val,
-                                                                       const uint8_t *deq_zone,
-                                                                       const uint8_t *row_of_bin,
-                                                                       const uint16_t *__restrict__ bsplit,
-                                                                       const int64_t *hdr, const int64_t *win_off,
-                                                                       const int32_t *tile_stream,
-                                                                       const uint8_t *symbols, const float *__restrict__ gamma,
-                                                                       float *out) {
-  using T = Traits<PREC>;
-  extern __shared__ __align__(16) unsigned char lds[];
-  const int nthreads = blockDim.x, waves = nthreads >> 6;
-  uint16_t *Bb = reinterpret_cast<uint16_t *>(lds);
-  float *Tv = reinterpret_cast<float *>(lds + block_basis_bytes(T::kBPieces));
-  uint8_t *Tz = reinterpret_cast<uint8_t *>(Tv + n_books * n_rows * 256);
-  uint8_t *Rb = Tz + n_books * n_rows * 256;
-  for (int i = threadIdx.x; i < n_books * n_rows * 256; i += nthreads) {
-    Tv[i] = deq_val[i];
-    const int z = deq_zone[i];
-    Tz[i] = (uint8_t)(z < 2 ? z : 2);
-  }
-  for (int i = threadIdx.x; i < n_books * E; i += nthreads) {
-    const int r = row_of_bin[i];
-    Rb[i] = (uint8_t)(r < n_rows ? r : n_rows - 1);
-  }
-  const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63, col = lane & 31, h = lane >> 5;
-  const int KH = S * 8, nblk = (S + kSB - 1) / kSB;
-  const int64_t n_win = hdr[1];
-  const int64_t n_tiles = (n_win + kTileWindows - 1) / kTileWindows;
-  const float oscale = 1.0f / (T::kF16 ? kBasisScaleF16 : 1.0f);
-
-  for (int64_t t0 = (int64_t)blockIdx.x * waves; t0 < n_tiles; t0 += (int64_t)gridDim.x * waves) {
-    const int64_t tile = t0 + wid;
-    const int64_t g = tile * kTileWindows + col;
-    int valid = 0, book = 0;
-    int64_t obase = 0;
-    float g0 = 1.0f, g1 = 1.0f, g2 = 1.0f;
-    if (tile < n_tiles && g < n_win) {
-      int s = tile_stream[tile];
-      s = s < 0 ? 0 : (s >= b.n_streams ? b.n_streams - 1 : s);
-      while (s + 1 < b.n_streams && win_off[s + 1] <= g) ++s;
-      const int64_t j = g - win_off[s];
-      const int64_t L = b.sample_off[s + 1] - b.sample_off[s];
-      const int64_t o = b.sample_off[s] + j * N256;
-      int64_t v = L - j * N256;
-      v = v < N256 ? v : N256;
-      if (o < 0 || o + v > b.n_samples || j < 0) v = 0;
-      valid = v > 0 ? (int)v : 0;
-      obase = o;
-      const int bk = b.book_id ? (int)b.book_id[s] : 0;
-      book = bk < n_books ? bk : 0;
-      if (gamma) {
-        g0 = gamma[3 * (int64_t)s];
-        g1 = gamma[3 * (int64_t)s + 1];
-        g2 = gamma[3 * (int64_t)s + 2];
-      }
-    }
-    f16v acc[NT256];
-#pragma unroll
-    for (int t = 0; t < NT256; ++t)
-#pragma unroll
-      for (int r = 0; r < 16; ++r) acc[t][r] = 0.0f;
-    const int64_t sbase = g * (int64_t)E;
-    auto sym = [&](int k0) {
-      uint32_t w[2] = {0u, 0u};
-#pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        const int64_t si = sbase + k0 + j;
-        const uint32_t v = (valid > 0 && k0 + j < E && si < b.n_symbols) ? symbols[si] : 128u;
-        w[j >> 2] |= v << (8 * (j & 3));
-      }
-      return make_uint2(w[0], w[1]);
-    };
-    for (int blk = nblk - 1; blk >= 0; --blk) {
-      __syncthreads();
-      copy_basis_block(Bb, bsplit + (size_t)blk * (block_basis_bytes(T::kBPieces) / 2),
-                       (int)block_basis_bytes(T::kBPieces), threadIdx.x, nthreads);
-      __syncthreads();
-      const int s1 = min(S, (blk + 1) * kSB);
-      contract_block256<PREC>(acc, Bb, blk * kSB, s1, KH, h, col, E, valid > 0, Rb + book * E,
-                              Tv + book * n_rows * 256, Tz + book * n_rows * 256, gamma != nullptr, g0, g1, g2, sym);
-    }
-    // the tile's windows may belong to different streams: each lane takes the
-    // output offset and length of the windows it holds from their own lanes
-    const int ob_lo = (int)(uint32_t)obase, ob_hi = (int)(obase >> 32);
-#pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      const int w = acc_window(r, h);
-      const int v_w = __shfl(valid, w);
-      const int64_t ob_w = ((int64_t)__shfl(ob_hi, w) << 32) | (int64_t)(uint32_t)__shfl(ob_lo, w);
-#pragma unroll
-      for (int t = 0; t < NT256; ++t) {
-        const int n = 32 * t + col;
-        if (n < v_w) out[ob_w + n] = acc[t][r] * oscale;
-      }
-    }
-  }
-}
-
-// ---------------------------------------------------------------- fused path
-// Dequantization tables: values, zones, row of each bin.
-__host__ __device__ inline size_t table256_bytes(int bp, int n_books, int n_rows, int E) {
-  (void)bp;
-  return a16((size_t)n_books * n_rows * 256 * 5 + (size_t)n_books * E);
-}
-
-__host__ __device__ inline size_t wave256_bytes(int wpc, int E) { return (size_t)kSymPrefix + a16((size_t)wpc * E + 16); }
-
-// LDS: lookup tables | staged basis block | dequantization tables | wave
-// buffers; the multi-symbol build borrows lut1_temp_bytes after the tables.
-__host__ __device__ inline size_t fused256_lds_ms(bool ms, int bp, int n_books, int lmax, int E, int wpc, int waves,
-                                                  int n_rows) {
-  const size_t t = lut_lds_bytes(ms, n_books, lmax);
-  const size_t need = t + block_basis_bytes(bp) + table256_bytes(bp, n_books, n_rows, E) +
-                      (size_t)waves * wave256_bytes(wpc, E);
-  const size_t tmp = ms ? t + lut1_temp_bytes(n_books, lmax) : 0;
+// LDS: [decode tables] | dequantization tables | slots | exchange buffers |
+// wave symbol buffers.  The multi-symbol table build borrows lut1_temp_bytes
+// right after the decode tables.
+__host__ __device__ inline size_t w256_lds(bool fused, bool ms, int ap, int n_books, int n_rows, int lmax, int E,
+                                           int wpc, int nxb) {
+  const size_t t = fused ? lut_lds_bytes(ms, n_books, lmax) : 0;
+  const size_t need = t + a16(deq_table_bytes(ap, n_books, n_rows, E)) + kWaves256 * sizeof(Slot) +
+                      (size_t)nxb * kWaves256 * kXchBytes + kWaves256 * wave256_bytes(wpc, E);
+  const size_t tmp = (fused && ms) ? t + lut1_temp_bytes(n_books, lmax) : 0;
   return need > tmp ? need : tmp;
 }
 
-template <int PREC, bool MS>
-__global__ void __launch_bounds__(kMaxWaves256 * 64) k_fused256(const uint64_t *__restrict__ words,
-                                                                 const uint8_t *__restrict__ symlen, int n_streams,
-                                                                 int E, int S, int lmax, int n_books, int n_rows,
-                                                                 int wpc, const uint16_t *__restrict__ lut_g,
-                                                                 const float *__restrict__ deq_val,
-                                                                 const uint8_t *__restrict__ deq_zone,
-                                                                 const uint8_t *__restrict__ row_of_bin,
-                                                                 const uint16_t *__restrict__ bsplit,
-                                                                 const int64_t *__restrict__ hdr,
-                                                                 const ChunkMeta *__restrict__ meta,
-                                                                 const float *__restrict__ gamma, float *out,
-                                                                 int32_t *status) {
+// The 8 bytes of parity p (bytes p, p + 2, ..., p + 14) of a 16-byte group.
+__device__ inline uint2 parity_bytes(uint4 u, int p) {
+  const uint32_t sel = p ? 0x07050301u : 0x06040200u;
+  return make_uint2(__builtin_amdgcn_perm(u.y, u.x, sel), __builtin_amdgcn_perm(u.w, u.z, sel));
+}
+
+// c += basis pieces x coefficient pieces for one k-step, smallest terms first
+// (the order of mfma_step).
+template <int PREC>
+__device__ inline f16v mfma_pieces(const u8v (&bp)[Traits<PREC>::kBPieces], const u8v (&a)[Traits<PREC>::kAPieces],
+                                   f16v c, bool any_rest) {
   using T = Traits<PREC>;
+  constexpr int BP = T::kBPieces;
+  if constexpr (BP == 3) {
+    c = mfma<T::kF16>(bp[2], a[0], c);
+    if (any_rest) {
+      c = mfma<T::kF16>(bp[1], a[1], c);
+      c = mfma<T::kF16>(bp[0], a[2], c);
+    }
+    c = mfma<T::kF16>(bp[1], a[0], c);
+    if (any_rest) c = mfma<T::kF16>(bp[0], a[1], c);
+  } else if constexpr (BP == 2) {
+    if (any_rest) c = mfma<T::kF16>(bp[0], a[1], c);
+    c = mfma<T::kF16>(bp[1], a[0], c);
+  }
+  return mfma<T::kF16>(bp[0], a[0], c);
+}
+
+// This wave's basis slice: for k-step s, lane (col, h) holds bins
+// 2 (64 h + 8 s + j) + p, j < 8, at column n0 + col, split into pieces (FP16
+// pieces scaled by 2^10); zero past E.
+template <int PREC>
+__device__ inline void load_basis_slice(u8v (&bv)[kMaxSteps][Traits<PREC>::kBPieces], const float *__restrict__ basis,
+                                        int E, int p, int n0, int col, int h) {
+  using T = Traits<PREC>;
+  constexpr int BP = T::kBPieces;
+  const float bscale = T::kF16 ? kBasisScaleF16 : 1.0f;
+#pragma unroll
+  for (int s = 0; s < kMaxSteps; ++s) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int k = 2 * (64 * h + 8 * s + j) + p;
+      const float v = k < E ? basis[(int64_t)k * N256 + n0 + col] * bscale : 0.0f;
+      uint16_t pc[BP];
+      split<T::kF16, BP>(v, pc);
+#pragma unroll
+      for (int q = 0; q < BP; ++q) bv[s][q][j] = pc[q];
+    }
+  }
+}
+
+// Coefficient forms of a kernel: the pre-split table with one or several
+// table rows (no per-stream scales, E = 256, at most two pieces), the general
+// dequantization with every bin kept (E = 256), or with bins past E masked.
+enum { kFormPresplit1 = 0, kFormPresplitRows = 1, kFormDequant = 2, kFormDequantE = 3 };
+
+// Partial sums of one parity for a 32-window tile: lane (col, h) supplies the
+// coefficients of window `col`, whose symbols start at sbw (bins 128 h + 16 s
+// + 2 j + p for k-step s); the result leaves lane (col, h) with column n0 +
+// col of windows acc_window(r, h).  All 8 k-steps run, from the highest bins
+// down; bins past E have a zero basis row and a zero coefficient.  The
+// symbol buffer holds at least 256 bytes past the start of any window, so
+// every read stays inside it.
+template <int PREC, int FORM>
+__device__ inline f16v contract_parity(const u8v (&bv)[kMaxSteps][Traits<PREC>::kBPieces], const unsigned char *sbw,
+                                       int p, int h, int E, bool valid, bool e_vec, const uint8_t *rb,
+                                       const float *tv, const uint8_t *tz, const uint32_t *pq, bool scaled, float g0,
+                                       float g1, float g2) {
+  using T = Traits<PREC>;
+  constexpr int AP = T::kAPieces;
+  const unsigned char *row = sbw + 128 * h;   // this lane's symbols, 16-byte aligned when e_vec
+  const int kh = 128 * h + p;                 // bin of step 0, j = 0
+  f16v acc = {};
+#pragma unroll
+  for (int s = kMaxSteps - 1; s >= 0; --s) {
+    uint2 u;
+    if (FORM != kFormDequantE || e_vec) {
+      u = parity_bytes(*reinterpret_cast<const uint4 *>(row + 16 * s), p);
+    } else {
+      uint32_t w[2] = {0u, 0u};
+#pragma unroll
+      for (int j = 0; j < 8; ++j) w[j >> 2] |= (uint32_t)row[p + 16 * s + 2 * j] << (8 * (j & 3));
+      u = make_uint2(w[0], w[1]);
+    }
+    u8v a[AP];
+    bool r;
+    if constexpr (FORM == kFormPresplit1 || FORM == kFormPresplitRows) {
+      r = gather8<PREC, FORM == kFormPresplitRows, 2>(u.x, u.y, kh + 16 * s, pq, rb, a) && valid;
+    } else {
+      uint8_t sy[8];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        sy[j] = (uint8_t)(u.x >> (8 * j));
+        sy[4 + j] = (uint8_t)(u.y >> (8 * j));
+      }
+      r = dequant8<PREC, 2, FORM == kFormDequantE>(sy, kh + 16 * s, E, valid, rb, tv, tz, scaled, g0, g1, g2, a);
+    }
+    const bool any_rest = AP > 1 && __any(r);
+    acc = mfma_pieces<PREC>(bv[s], a, acc, any_rest);
+  }
+  return acc;
+}
+
+template <int PREC, bool FUSED, bool MS, int FORM>
+__global__ void __launch_bounds__(kWaves256 * 64) k_w256(const uint64_t *__restrict__ words,
+                                                        const uint8_t *__restrict__ symlen,
+                                                        const uint8_t *__restrict__ symbols, int64_t n_symbols,
+                                                        int n_streams, int E, int lmax, int n_books, int n_rows,
+                                                        int wpc, int nxb, const uint16_t *__restrict__ lut_g,
+                                                        const float *__restrict__ deq_val,
+                                                        const uint8_t *__restrict__ deq_zone,
+                                                        const uint8_t *__restrict__ row_of_bin,
+                                                        const float *__restrict__ basis,
+                                                        const int64_t *__restrict__ hdr,
+                                                        const ChunkMeta *__restrict__ meta,
+                                                        const float *__restrict__ gamma, float *out, int32_t *status) {
+  using T = Traits<PREC>;
+  constexpr int AP = T::kAPieces, BP = T::kBPieces;
   extern __shared__ __align__(16) unsigned char lds[];
-  const int nthreads = blockDim.x, waves = nthreads >> 6;
-  const size_t lut_bytes = lut_lds_bytes(MS, n_books, lmax);
-  uint16_t *Bb = reinterpret_cast<uint16_t *>(lds + lut_bytes);
-  float *Tv = reinterpret_cast<float *>(reinterpret_cast<unsigned char *>(Bb) + block_basis_bytes(T::kBPieces));
-  uint8_t *Tz = reinterpret_cast<uint8_t *>(Tv + n_books * n_rows * 256);
-  uint8_t *Rb = Tz + n_books * n_rows * 256;
-  unsigned char *wave_base = reinterpret_cast<unsigned char *>(Tv) + table256_bytes(T::kBPieces, n_books, n_rows, E);
-  stage_decode_tables(MS, lds, lds + lut_bytes, lut_g, lmax, n_books, threadIdx.x, nthreads);
-  for (int i = threadIdx.x; i < n_books * n_rows * 256; i += nthreads) {
-    Tv[i] = deq_val[i];
-    const int z = deq_zone[i];
-    Tz[i] = (uint8_t)(z < 2 ? z : 2);
-  }
-  for (int i = threadIdx.x; i < n_books * E; i += nthreads) {
-    const int r = row_of_bin[i];
-    Rb[i] = (uint8_t)(r < n_rows ? r : n_rows - 1);
-  }
-  __syncthreads();
-  const bool e_vec = (E % 16) == 0;
+  const size_t lut_bytes = FUSED ? lut_lds_bytes(MS, n_books, lmax) : 0;
+  unsigned char *tables = lds + lut_bytes;
+  const DeqTables dt = deq_tables_at(tables, n_books, n_rows, E);
+  Slot *slots = reinterpret_cast<Slot *>(tables + a16(deq_table_bytes(AP, n_books, n_rows, E)));
+  float *xch = reinterpret_cast<float *>(slots + kWaves256);
+  unsigned char *wave_base = reinterpret_cast<unsigned char *>(xch) + (size_t)nxb * kWaves256 * kXchBytes;
+
+  if constexpr (FUSED) stage_decode_tables(MS, lds, lds + lut_bytes, lut_g, lmax, n_books, threadIdx.x, blockDim.x);
+  stage_deq_tables<PREC>(dt, deq_val, deq_zone, row_of_bin, n_books, n_rows, E, threadIdx.x, blockDim.x);
+
   const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63, col = lane & 31, h = lane >> 5;
-  unsigned char *sb = wave_base + (size_t)wid * wave256_bytes(wpc, E) + kSymPrefix;
-  const uint8_t *cl = lds + ((size_t)n_books << lmax) * 4;
-  const uint32_t *binfo = reinterpret_cast<const uint32_t *>(cl + n_books * 256);  // multi-symbol form only
-  const int hs = 32 - lmax;
-  const int KH = S * 8, nblk = (S + kSB - 1) / kSB;
-  const int ntile_max = (wpc + kTileWindows - 1) / kTileWindows;
+  const int p = wid >> 2, ct = wid & 3;
+  const int n0 = 32 * ct;
+  unsigned char *const sb_own = wave_base + (size_t)wid * wave256_bytes(wpc, E) + kSymPrefix;
   const float oscale = 1.0f / (T::kF16 ? kBasisScaleF16 : 1.0f);
+  const bool e_vec = (E % 16) == 0;
+  const bool sym_vec = e_vec && (reinterpret_cast<uintptr_t>(symbols) & 15) == 0;
   const int64_t n_chunks = hdr[0];
-  const int64_t cstride = (int64_t)gridDim.x * waves;
+  const int64_t rstride = (int64_t)gridDim.x * kWaves256;
 
-  // Software pipeline over this wave's chunks (see the resident fused
-  // kernel): next chunk's words requested before this chunk decodes, waited
-  // for right after the decode, before this chunk's stores.
-  ChunkMeta cm, nm;
-  ChunkWords cw{};
-  {
-    const int64_t c = (int64_t)blockIdx.x * waves + wid;
-    cm = meta_from_lanes(load_meta_lane(meta, c, n_chunks, lane), c < n_chunks);
-    const uint32_t vn = load_meta_lane(meta, c + cstride, n_chunks, lane);
+  u8v bv[kMaxSteps][BP];
+  load_basis_slice<PREC>(bv, basis, E, p, n0, col, h);
+
+  const uint8_t *cl = FUSED ? lds + ((size_t)n_books << lmax) * 4 : nullptr;
+  const uint32_t *binfo = FUSED ? reinterpret_cast<const uint32_t *>(cl + n_books * 256) : nullptr;
+  const int hs = 32 - lmax;
+
+  // this wave's chunk of the first round, its words (or symbols), and the
+  // record of its chunk in the next round
+  int64_t c = (int64_t)blockIdx.x * kWaves256 + wid;
+  ChunkMeta cm = meta_from_lanes(load_meta_lane(meta, c, n_chunks, lane), c < n_chunks);
+  ChunkWordsT<kPre256> cw{};
+  uint4 sv[kSymVec];
+  auto load_syms = [&](const ChunkMeta &m, bool ok) {
+    const int nbytes = ok ? min(m.n_windows, 32) * E : 0;
+#pragma unroll
+    for (int i = 0; i < kSymVec; ++i) {
+      const int off = 16 * (lane + 64 * i);
+      sv[i] = make_uint4(0u, 0u, 0u, 0u);
+      if (off < nbytes) {
+        const int64_t g = m.sym_base + off;
+        if (sym_vec && g + 16 <= n_symbols) {
+          sv[i] = *reinterpret_cast<const uint4 *>(symbols + g);
+        } else {
+          uint32_t w[4] = {0u, 0u, 0u, 0u};
+          for (int j = 0; j < 16; ++j)
+            if (g + j < n_symbols) w[j >> 2] |= (uint32_t)symbols[g + j] << (8 * (j & 3));
+          sv[i] = make_uint4(w[0], w[1], w[2], w[3]);
+        }
+      }
+    }
+  };
+  if constexpr (FUSED) {
     if (c < n_chunks) load_chunk_words(words, symlen, cm.first_word, cm.word_end, lane, cw);
-    nm = meta_from_lanes(vn, c + cstride < n_chunks);
+  } else {
+    load_syms(cm, c < n_chunks);
   }
-  for (int64_t c0 = (int64_t)blockIdx.x * waves; c0 < n_chunks; c0 += cstride) {
-    const int64_t c = c0 + wid;
-    const bool active = c < n_chunks && cm.first_word >= 0;
-    const int s = cm.stream < 0 ? 0 : (cm.stream >= n_streams ? n_streams - 1 : cm.stream);
+  uint32_t vn = load_meta_lane(meta, c + rstride, n_chunks, lane);
+
+#pragma unroll 1
+  for (int64_t c0 = (int64_t)blockIdx.x * kWaves256; c0 < n_chunks; c0 += rstride) {
+    c = c0 + wid;
+    // ---- 1. this wave's chunk of the round into its LDS buffer
+    const bool have = c < n_chunks && (!FUSED || cm.first_word >= 0);
+    const int s_id = cm.stream < 0 ? 0 : (cm.stream >= n_streams ? n_streams - 1 : cm.stream);
     const int book = cm.book < n_books && cm.book >= 0 ? cm.book : 0;
-    const int w_cnt = active ? cm.n_windows : 0;
-    const float vg = load_gamma_lane(active ? gamma : nullptr, s, lane);
-    const uint32_t vm = load_meta_lane(meta, c + 2 * cstride, n_chunks, lane);
-    ChunkWords nx{};
-    if (c + cstride < n_chunks) load_chunk_words(words, symlen, nm.first_word, nm.word_end, lane, nx);
-    int err = 0;
-    if (active) {
-      const void *lb = MS ? (const void *)(reinterpret_cast<const uint32_t *>(lds) + (book << lmax))
-                          : (const void *)(reinterpret_cast<const uint16_t *>(lds) + (book << lmax));
-      err = decode_chunk<MS>(words, symlen, cm.first_word, cm.first_sym, w_cnt * E, cm.word_end, cw, lb,
-                             cl + book * 256, MS ? binfo[book] : 0u, hs, sb, lane);
+    const float vg = load_gamma_lane(have ? gamma : nullptr, s_id, lane);
+    if constexpr (FUSED) {
+      if (have) {
+        const void *lb = MS ? (const void *)(reinterpret_cast<const uint32_t *>(lds) + (book << lmax))
+                            : (const void *)(reinterpret_cast<const uint16_t *>(lds) + (book << lmax));
+        const int err = decode_chunk<MS, kPre256>(words, symlen, cm.first_word, cm.first_sym, cm.n_windows * E,
+                                                  cm.word_end, cw, lb, cl + book * 256, MS ? binfo[book] : 0u, hs,
+                                                  sb_own, lane);
+        if (err && status) atomicOr(&status[s_id], err);
+      }
+    } else {
+      if (have) {
+        const int nbytes = cm.n_windows * E;
+#pragma unroll
+        for (int i = 0; i < kSymVec; ++i) {
+          const int off = 16 * (lane + 64 * i);
+          if (off < nbytes && off < 32 * E) *reinterpret_cast<uint4 *>(sb_own + off) = sv[i];
+        }
+        // windows past the first 32 (wpc > 32): straight from memory
+        for (int off = 32 * E + lane; off < nbytes; off += 64) {
+          const int64_t g = cm.sym_base + off;
+          sb_own[off] = g < n_symbols ? symbols[g] : (uint8_t)128;
+        }
+      }
     }
-    settle_chunk_words(nx);
-    settle_lane(vm);
     settle_lane(vg);
-    const ChunkMeta mm = meta_from_lanes(vm, c + 2 * cstride < n_chunks);
-    cw = nx;
-    if (err && status) atomicOr(&status[s], err);
-    const float g0 = lane_float(vg, 0), g1 = lane_float(vg, 1), g2 = lane_float(vg, 2);
-    wave_sync_lds();
-    for (int tt = 0; tt < ntile_max; ++tt) {
-      const int wr = tt * kTileWindows + col;
-      const int valid = wr < w_cnt ? min(N256, cm.out_len - wr * N256) : 0;
-      const int base = (wr < w_cnt ? wr : (w_cnt > 0 ? w_cnt - 1 : 0)) * E;
-      f16v acc[NT256];
-#pragma unroll
-      for (int t = 0; t < NT256; ++t)
-#pragma unroll
-        for (int r = 0; r < 16; ++r) acc[t][r] = 0.0f;
-      const bool tile_active = tt * kTileWindows < w_cnt;
-      auto sym = [&](int k0) {
-        if (e_vec) return *reinterpret_cast<const uint2 *>(sb + base + k0);
-        uint32_t w[2] = {0u, 0u};
-#pragma unroll
-        for (int j = 0; j < 8; ++j) w[j >> 2] |= (uint32_t)sb[base + (k0 + j < E ? k0 + j : 0)] << (8 * (j & 3));
-        return make_uint2(w[0], w[1]);
-      };
-      for (int blk = nblk - 1; blk >= 0; --blk) {
-        __syncthreads();
-        copy_basis_block(Bb, bsplit + (size_t)blk * (block_basis_bytes(T::kBPieces) / 2),
-                       (int)block_basis_bytes(T::kBPieces), threadIdx.x, nthreads);
-        __syncthreads();
-        if (tile_active)
-          contract_block256<PREC>(acc, Bb, blk * kSB, min(S, (blk + 1) * kSB), KH, h, col, E, valid > 0,
-                                  Rb + book * E, Tv + book * n_rows * 256, Tz + book * n_rows * 256,
-                                  gamma != nullptr, g0, g1, g2, sym);
+    settle_lane(vn);
+    const ChunkScales cs = chunk_scales<PREC>(gamma, lane_float(vg, 0), lane_float(vg, 1), lane_float(vg, 2),
+                                              dt.vmax[book], oscale);
+    if (lane == 0) {
+      Slot sl;
+      sl.out_base = cm.out_base;
+      sl.out_len = cm.out_len;
+      sl.n_win = have ? cm.n_windows : 0;
+      sl.book = book;
+      sl.scaled = cs.scaled ? 1 : 0;
+      sl.g0 = cs.g0;
+      sl.g1 = cs.g1;
+      sl.g2 = cs.g2;
+      sl.oscale = cs.out;
+      slots[wid] = sl;
+    }
+    // the next round's chunk: its record (requested a round ago) and words
+    const int64_t cn = c + rstride;
+    cm = meta_from_lanes(vn, cn < n_chunks);
+    vn = load_meta_lane(meta, cn + rstride, n_chunks, lane);
+    if constexpr (FUSED) {
+      cw = ChunkWordsT<kPre256>{};
+      if (cn < n_chunks) load_chunk_words(words, symlen, cm.first_word, cm.word_end, lane, cw);
+    } else {
+      load_syms(cm, cn < n_chunks);
+    }
+    __syncthreads();
+
+    // ---- 2. every 32-window tile of the round's chunks
+    bool first = true;
+    int xb = 0;
+#pragma unroll 1
+    for (int j = 0; j < kWaves256; ++j) {
+      const Slot &slj = slots[j];
+      const int n_win = __builtin_amdgcn_readfirstlane(slj.n_win);
+      if (n_win <= 0) continue;
+      const int book_j = __builtin_amdgcn_readfirstlane(slj.book);
+      const int out_len = __builtin_amdgcn_readfirstlane(slj.out_len);
+      const int64_t out_base = (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(slj.out_base >> 32))
+                                          << 32) |
+                                         (uint32_t)__builtin_amdgcn_readfirstlane((int)slj.out_base));
+      const float os = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(slj.oscale)));
+      bool scaled = false;
+      float g0 = 1.0f, g1 = 1.0f, g2 = 1.0f;
+      if constexpr (FORM == kFormDequant || FORM == kFormDequantE) {
+        scaled = __builtin_amdgcn_readfirstlane(slj.scaled) != 0;
+        g0 = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(slj.g0)));
+        g1 = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(slj.g1)));
+        g2 = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(slj.g2)));
       }
-      float *win0 = out + cm.out_base + (int64_t)tt * kTileWindows * N256;
-      const int rem = tile_active ? cm.out_len - tt * kTileWindows * N256 : 0;
-      if (E == N256 && wpc >= kTileWindows && tile_active) {  // stage through the consumed symbol buffer
-        if (rem >= kTileWindows * N256)
-          store_tile_whole<NT256>(win0, acc, reinterpret_cast<float *>(sb) - 4, h, col, lane, oscale);
-        else
-          store_tile_staged<NT256>(win0, acc, reinterpret_cast<float *>(sb) - 4, h, col, lane, rem, oscale);
-      } else {
+      const unsigned char *sb = wave_base + (size_t)j * wave256_bytes(wpc, E) + kSymPrefix;
+      const uint8_t *rb = dt.rb + book_j * E;
+      const float *tv = dt.tv + book_j * n_rows * 256;
+      const uint8_t *tz = dt.tz + book_j * n_rows * 256;
+      const uint32_t *pq = dt.pq + book_j * n_rows * 256;
+#pragma unroll 1
+      for (int tt = 0; tt * kTileWindows < n_win; ++tt) {
+        const int wr = tt * kTileWindows + col;  // chunk-relative window of this lane's A row
+        const bool valid = wr < n_win;
+        const f16v acc = contract_parity<PREC, FORM>(bv, sb + (valid ? wr : n_win - 1) * E, p, h, E, valid, e_vec,
+                                                     rb, tv, tz, pq, scaled, g0, g1, g2);
+        if (first) {  // the next round's loads have arrived by now; wait before any store
+          if constexpr (FUSED) {
+            settle_chunk_words(cw);
+          } else {
 #pragma unroll
-        for (int t = 0; t < NT256; ++t) store_rows(win0, N256, acc[t], t, h, col, rem, oscale);
+            for (int i = 0; i < kSymVec; ++i)
+              asm volatile("" ::"v"(sv[i].x), "v"(sv[i].y), "v"(sv[i].z), "v"(sv[i].w) : "memory");
+          }
+          first = false;
+        }
+        // swap partial sums with the other parity's wave of this column tile
+        float *mine = xch + ((size_t)xb * kWaves256 + wid) * (kXchBytes / 4);
+        const float *theirs = xch + ((size_t)xb * kWaves256 + (wid ^ 4)) * (kXchBytes / 4);
+        if (nxb == 1) __syncthreads();  // the buffer's previous readers are done
+#pragma unroll
+        for (int r = 0; r < 16; ++r) mine[r * 64 + lane] = acc[r];
+        __syncthreads();
+        const int n = p ? N256 - 1 - (n0 + col) : n0 + col;
+        float *win0 = out + out_base + (int64_t)tt * kTileWindows * N256;
+        const int rem = out_len - tt * kTileWindows * N256;  // samples from win0 to the chunk's end
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const float o = theirs[r * 64 + lane];
+          const float x = p ? o - acc[r] : acc[r] + o;
+          const int off = acc_window(r, h) * N256 + n;
+          if (off < rem) win0[off] = x * os;
+        }
+        xb ^= nxb - 1;
       }
     }
-    wave_sync_lds();
-    cm = nm;
-    nm = mm;
+    // every wave is done with this round's slots, symbols and exchange
+    // buffers before the next round overwrites them
+    __syncthreads();
   }
 }
 
 int pieces(int precision) { return precision == FPTC_BF16X3 ? 3 : (precision == FPTC_FP16X2 ? 2 : 1); }
 
-size_t split256_lds(int bp, const fptc_codec &c) {
-  return block_basis_bytes(bp) + a16((size_t)c.n_books * c.n_rows * 256 * 5 + (size_t)c.n_books * c.E);
-}
-
-size_t fused256_lds(int bp, const fptc_codec &c, int wpc, int waves, int n_rows) {
-  return fused256_lds_ms(false, bp, c.n_books, c.lmax, c.E, wpc, waves, n_rows);
+template <int PREC, int FORM>
+int attrs_form() {
+  return lds_attr(k_w256<PREC, false, false, FORM>) | lds_attr(k_w256<PREC, true, true, FORM>) |
+         lds_attr(k_w256<PREC, true, false, FORM>);
 }
 
 template <int PREC>
 int attrs_prec() {
-  return lds_attr(k_dqidct_mfma256<PREC>) | lds_attr(k_fused256<PREC, true>) | lds_attr(k_fused256<PREC, false>);
+  int rc = attrs_form<PREC, kFormDequant>() | attrs_form<PREC, kFormDequantE>();
+  if constexpr (Traits<PREC>::kAPieces <= 2) rc |= attrs_form<PREC, kFormPresplit1>() | attrs_form<PREC, kFormPresplitRows>();
+  return rc;
 }
 
-// Split the basis into the workspace (one workgroup per staged block).
-template <int PREC>
-int split_basis(const fptc_codec &c, int S, const Plan &p, void *stream) {
-  const int nblk = (S + kSB - 1) / kSB;
-  hipLaunchKernelGGL(k_split_basis256<PREC>, dim3(nblk), dim3(256), 0, (hipStream_t)stream, c.basis, c.E, S * 8,
-                     p.basis_split);
+// Double exchange buffers (one barrier per tile) when they fit, else one.
+int exchange_buffers(bool fused, bool ms, int ap, const fptc_codec &c, int wpc) {
+  if (w256_lds(fused, ms, ap, c.n_books, c.n_rows, c.lmax, c.E, wpc, 2) <= 160 * 1024) return 2;
+  if (w256_lds(fused, ms, ap, c.n_books, c.n_rows, c.lmax, c.E, wpc, 1) <= 160 * 1024) return 1;
+  return 0;
+}
+
+template <int PREC, bool FUSED, bool MS, int FORM>
+int launch_form(const fptc_batch &b, const fptc_codec &c, const Shape &sh, const Plan &p, const uint8_t *symbols,
+                const float *gamma, float *out, int32_t *status, void *stream) {
+  constexpr int AP = Traits<PREC>::kAPieces;
+  const int nxb = exchange_buffers(FUSED, MS, AP, c, sh.wpc);
+  if (!nxb) return (int)hipErrorInvalidValue;
+  const size_t lds = w256_lds(FUSED, MS, AP, c.n_books, c.n_rows, c.lmax, c.E, sh.wpc, nxb);
+  const int blocks = sh.blocks > 0 ? sh.blocks : device_cu_count();
+  hipLaunchKernelGGL((k_w256<PREC, FUSED, MS, FORM>), dim3(blocks), dim3(kWaves256 * 64), lds, (hipStream_t)stream,
+                     b.words, b.symlen, symbols, b.n_symbols, b.n_streams, c.E, c.lmax, c.n_books, c.n_rows, sh.wpc,
+                     nxb, c.lut, c.deq_val, c.deq_zone, c.row_of_bin, c.basis, p.hdr, p.chunk_meta, gamma, out,
+                     status);
   return (int)hipGetLastError();
 }
 
-template <int PREC>
-int launch_split(const fptc_batch &b, const fptc_codec &c, const Shape &sh, const Plan &p, const uint8_t *symbols,
-                 const float *gamma, float *out, void *stream) {
-  const int S = (c.E + 15) / 16;
-  int rc = split_basis<PREC>(c, S, p, stream);
-  if (rc) return rc;
-  const size_t lds = split256_lds(Traits<PREC>::kBPieces, c);
-  const int per_cu = (int)((160 * 1024) / lds);
-  const int blocks = sh.blocks > 0 ? sh.blocks : device_cu_count() * (per_cu < 1 ? 1 : per_cu);
-  hipLaunchKernelGGL(k_dqidct_mfma256<PREC>, dim3(blocks), dim3(kMaxWaves256 * 64), lds, (hipStream_t)stream, b,
-                     c.E, S, c.n_books, c.n_rows, c.deq_val, c.deq_zone, c.row_of_bin, p.basis_split, p.hdr, p.win_off,
-                     p.tile_stream, symbols, gamma, out);
-  return (int)hipGetLastError();
+// The coefficient form: the pre-split table when there are no per-stream
+// scales, every bin is kept and at most two pieces are needed; otherwise
+// dequantization, masking bins past E only when some are dropped.
+template <int PREC, bool FUSED, bool MS>
+int launch_t(const fptc_batch &b, const fptc_codec &c, const Shape &sh, const Plan &p, const uint8_t *symbols,
+             const float *gamma, float *out, int32_t *status, void *stream) {
+  if constexpr (Traits<PREC>::kAPieces <= 2) {
+    if (!gamma && c.E == N256) {
+      if (c.n_rows > 1)
+        return launch_form<PREC, FUSED, MS, kFormPresplitRows>(b, c, sh, p, symbols, gamma, out, status, stream);
+      return launch_form<PREC, FUSED, MS, kFormPresplit1>(b, c, sh, p, symbols, gamma, out, status, stream);
+    }
+  }
+  if (c.E == N256) return launch_form<PREC, FUSED, MS, kFormDequant>(b, c, sh, p, symbols, gamma, out, status, stream);
+  return launch_form<PREC, FUSED, MS, kFormDequantE>(b, c, sh, p, symbols, gamma, out, status, stream);
 }
 
-template <int PREC, bool MS>
-int launch_fused_t(const fptc_batch &b, const fptc_codec &c, const Shape &sh, const Plan &p, const float *gamma,
-                   float *out, int32_t *status, void *stream) {
-  const int S = (c.E + 15) / 16;
-  int rc = split_basis<PREC>(c, S, p, stream);
-  if (rc) return rc;
-  const size_t lds = fused256_lds_ms(MS, Traits<PREC>::kBPieces, c.n_books, c.lmax, c.E, sh.wpc, sh.waves, c.n_rows);
-  const int per_cu = (int)((160 * 1024) / lds);
-  const int blocks = sh.blocks > 0 ? sh.blocks : device_cu_count() * (per_cu < 1 ? 1 : per_cu);
-  auto kern = k_fused256<PREC, MS>;
-  hipLaunchKernelGGL(kern, dim3(blocks), dim3(sh.waves * 64), lds, (hipStream_t)stream, b.words,
-                     b.symlen, b.n_streams, c.E, S, c.lmax, c.n_books, c.n_rows, sh.wpc, c.lut, c.deq_val,
-                     c.deq_zone, c.row_of_bin, p.basis_split, p.hdr, p.chunk_meta, gamma, out, status);
-  return (int)hipGetLastError();
-}
-
-// Multi-symbol decode tables when they fit beside everything else.
 template <int PREC>
-int launch_fused_ms(const fptc_batch &b, const fptc_codec &c, const Shape &sh, const Plan &p, const float *gamma,
-                    float *out, int32_t *status, void *stream) {
-  if (fused256_lds_ms(true, Traits<PREC>::kBPieces, c.n_books, c.lmax, c.E, sh.wpc, sh.waves, c.n_rows) <=
-      160 * 1024)
-    return launch_fused_t<PREC, true>(b, c, sh, p, gamma, out, status, stream);
-  return launch_fused_t<PREC, false>(b, c, sh, p, gamma, out, status, stream);
+int launch_fused_prec(const fptc_batch &b, const fptc_codec &c, const Shape &sh, const Plan &p, const float *gamma,
+                      float *out, int32_t *status, void *stream) {
+  // multi-symbol decode tables when they fit beside everything else
+  if (exchange_buffers(true, true, Traits<PREC>::kAPieces, c, sh.wpc))
+    return launch_t<PREC, true, true>(b, c, sh, p, nullptr, gamma, out, status, stream);
+  return launch_t<PREC, true, false>(b, c, sh, p, nullptr, gamma, out, status, stream);
 }
 
 }  // namespace
@@ -416,25 +451,25 @@ int set_mfma256_attributes() {
   return attrs_prec<FPTC_FP16>() | attrs_prec<FPTC_FP16X2>() | attrs_prec<FPTC_BF16>() | attrs_prec<FPTC_BF16X3>();
 }
 
-bool mfma256_supported(int E, int precision) {
+bool mfma256_supported(const fptc_codec &c, int precision, int wpc) {
   if (precision < FPTC_FP16 || precision > FPTC_BF16X3) return false;
-  return E >= 1 && E <= N256;
+  if (c.E < 1 || c.E > N256) return false;
+  return exchange_buffers(false, false, pieces(precision), c, wpc) > 0;
 }
 
-size_t basis_split256_bytes(int N) { return N == N256 ? (size_t)kMaxBlocks256 * block_basis_bytes(3) : 0; }
-
 bool fused256_supported(const fptc_codec &c, int precision, int wpc, int waves) {
-  if (!mfma256_supported(c.E, precision) || waves < 1 || waves > kMaxWaves256) return false;
-  return fused256_lds(pieces(precision), c, wpc, waves, c.n_rows) <= 160 * 1024;
+  if (precision < FPTC_FP16 || precision > FPTC_BF16X3 || waves != kWaves256) return false;
+  if (c.E < 1 || c.E > N256) return false;
+  return exchange_buffers(true, false, pieces(precision), c, wpc) > 0;
 }
 
 int launch_dqidct_mfma256(const fptc_batch &b, const fptc_codec &c, const Shape &s, const Plan &p,
                           const uint8_t *symbols, const float *gamma, int precision, float *out, void *stream) {
   switch (precision) {
-    case FPTC_FP16: return launch_split<FPTC_FP16>(b, c, s, p, symbols, gamma, out, stream);
-    case FPTC_FP16X2: return launch_split<FPTC_FP16X2>(b, c, s, p, symbols, gamma, out, stream);
-    case FPTC_BF16: return launch_split<FPTC_BF16>(b, c, s, p, symbols, gamma, out, stream);
-    case FPTC_BF16X3: return launch_split<FPTC_BF16X3>(b, c, s, p, symbols, gamma, out, stream);
+    case FPTC_FP16: return launch_t<FPTC_FP16, false, false>(b, c, s, p, symbols, gamma, out, nullptr, stream);
+    case FPTC_FP16X2: return launch_t<FPTC_FP16X2, false, false>(b, c, s, p, symbols, gamma, out, nullptr, stream);
+    case FPTC_BF16: return launch_t<FPTC_BF16, false, false>(b, c, s, p, symbols, gamma, out, nullptr, stream);
+    case FPTC_BF16X3: return launch_t<FPTC_BF16X3, false, false>(b, c, s, p, symbols, gamma, out, nullptr, stream);
     default: return (int)hipErrorInvalidValue;
   }
 }
@@ -442,10 +477,10 @@ int launch_dqidct_mfma256(const fptc_batch &b, const fptc_codec &c, const Shape 
 int launch_fused256(const fptc_batch &b, const fptc_codec &c, const Shape &s, const Plan &p, const float *gamma,
                     int precision, float *out, int32_t *status, void *stream) {
   switch (precision) {
-    case FPTC_FP16: return launch_fused_ms<FPTC_FP16>(b, c, s, p, gamma, out, status, stream);
-    case FPTC_FP16X2: return launch_fused_ms<FPTC_FP16X2>(b, c, s, p, gamma, out, status, stream);
-    case FPTC_BF16: return launch_fused_ms<FPTC_BF16>(b, c, s, p, gamma, out, status, stream);
-    case FPTC_BF16X3: return launch_fused_ms<FPTC_BF16X3>(b, c, s, p, gamma, out, status, stream);
+    case FPTC_FP16: return launch_fused_prec<FPTC_FP16>(b, c, s, p, gamma, out, status, stream);
+    case FPTC_FP16X2: return launch_fused_prec<FPTC_FP16X2>(b, c, s, p, gamma, out, status, stream);
+    case FPTC_BF16: return launch_fused_prec<FPTC_BF16>(b, c, s, p, gamma, out, status, stream);
+    case FPTC_BF16X3: return launch_fused_prec<FPTC_BF16X3>(b, c, s, p, gamma, out, status, stream);
     default: return (int)hipErrorInvalidValue;
   }
 }

@@ -77,14 +77,15 @@ __device__ inline f16v mfma(u8v basis, u8v coef, f16v acc) {
 // Window (row of the 32 x 32 block) of accumulator element r in lane half h.
 __device__ inline int acc_window(int r, int h) { return 8 * (r >> 2) + 4 * h + (r & 3); }
 
-// Dequantize the 8 coefficients of one k-step (bins k0 + j, symbols sy) and
-// split each into the precision's 16-bit pieces a[p].  Returns whether any
+// Dequantize the 8 coefficients of one k-step (bins k0 + KS j, symbols sy) and
+// split each into the precision's 16-bit pieces a[p].  MASK: bins may reach
+// past E (zero coefficients there); else every bin is below E.  Returns whether any
 // lower piece is nonzero (a coefficient not exact in one piece).
 //   rb: row of each bin (rb[0 .. E)), tv/tz: value and zone of (row, symbol),
 //   g0..g2: the stream's per-zone scales (used when scaled).
 // Loads use clamped indices and the value is selected afterwards, so there
 // are no per-coefficient branches.
-template <int PREC>
+template <int PREC, int KS = 1, bool MASK = true>
 __device__ inline bool dequant8(const uint8_t (&sy)[8], int k0, int E, bool valid, const uint8_t *rb, const float *tv,
                                 const uint8_t *tz, bool scaled, float g0, float g1, float g2,
                                 u8v (&a)[Traits<PREC>::kAPieces]) {
@@ -93,14 +94,14 @@ __device__ inline bool dequant8(const uint8_t (&sy)[8], int k0, int E, bool vali
   bool rest = false;
 #pragma unroll
   for (int j = 0; j < 8; ++j) {
-    const int k = k0 + j;
-    const int ti = rb[k < E ? k : E - 1] * 256 + sy[j];
+    const int k = k0 + KS * j;
+    const int ti = rb[(!MASK || k < E) ? k : E - 1] * 256 + sy[j];
     float c = tv[ti];
     if (scaled) {
       const int z = tz[ti];
       c *= z == 0 ? g0 : (z == 1 ? g1 : g2);
     }
-    c = (valid && k < E) ? c : 0.0f;
+    c = (valid && (!MASK || k < E)) ? c : 0.0f;
     uint16_t pc[AP];
     split<T::kF16, AP>(c, pc);
 #pragma unroll
@@ -111,28 +112,133 @@ __device__ inline bool dequant8(const uint8_t (&sy)[8], int k0, int E, bool vali
   return rest;
 }
 
+// FP16 operand range.  Coefficients are split into FP16 pieces, whose range
+// ends at 65504, and a table value times a per-zone scale can lie far outside
+// it (the paper quantizer's values reach the clipped zone maxima A0 / A1 of
+// |c|, in the signal's own units).  So each chunk multiplies its coefficients
+// by 2^-e, e chosen from its codebook's largest |value| times its stream's
+// largest |scale| so that they lie below 2^15, and its output by 2^e.  A
+// power-of-two factor changes no significand and the FP32 sums scale exactly
+// with it, so results are those of unscaled arithmetic wherever that stays in
+// range.  BF16 shares FP32's exponent range: e = 0.
+template <int PREC>
+__device__ inline int coef_exp(float vmax) {
+  if constexpr (!Traits<PREC>::kF16) {
+    return 0;
+  } else {
+    if (!(vmax > 0.0f) || !(vmax <= 3.0e38f)) return 0;  // zero, NaN or infinite: leave unscaled
+    const int e = ((__float_as_int(vmax) >> 23) & 255) - 127 - 14;  // vmax * 2^-e in [2^14, 2^15)
+    return e < -100 ? -100 : (e > 100 ? 100 : e);
+  }
+}
+__device__ inline float pow2f(int e) { return __int_as_float((e + 127) << 23); }  // -126 <= e <= 127
+
+// Largest |value| of each codebook's table (vmax[book]): LDS, zeroed, then
+// raised by atomicMax on the float bits (non-negative floats order like
+// their bit patterns).
+__device__ inline void note_table_max(float *vmax, int book, float v) {
+  atomicMax(reinterpret_cast<unsigned *>(vmax) + book, __float_as_uint(fabsf(v)));
+}
+
 // Table of pre-split dequantized values for the unscaled path (at most two
 // pieces): one 32-bit entry per (book, row, symbol), the high piece in the
 // low half and the low piece in the high half, exactly what dequant8 would
-// produce for that symbol.
+// produce for that symbol at the book's coefficient exponent (coef_exp of
+// vmax[book]).  per_book: entries per codebook.
 template <int PREC>
-__device__ inline void stage_pieces(uint32_t *pq, const float *deq_val, int n, int tid, int nthreads) {
+__device__ inline void stage_pieces(uint32_t *pq, const float *deq_val, const float *vmax, int per_book, int n, int tid,
+                                    int nthreads) {
   using T = Traits<PREC>;
   constexpr int AP = T::kAPieces;
   static_assert(AP <= 2, "pre-split table holds at most two pieces");
   for (int i = tid; i < n; i += nthreads) {
     uint16_t pc[AP];
-    split<T::kF16, AP>(deq_val[i], pc);
+    split<T::kF16, AP>(deq_val[i] * pow2f(-coef_exp<PREC>(vmax[i / per_book])), pc);
     pq[i] = (uint32_t)pc[0] | (AP > 1 ? (uint32_t)pc[AP - 1] << 16 : 0u);
   }
+}
+
+// Dequantization tables of a workgroup in LDS: value and zone of each (book,
+// row, symbol), the row of each bin, the largest |value| per book and, for at
+// most two pieces, the pre-split values.
+struct DeqTables {
+  float *tv;
+  uint8_t *tz;
+  uint8_t *rb;
+  float *vmax;   // [kMaxBooks]
+  uint32_t *pq;  // pre-split values (at most two pieces)
+};
+
+__host__ __device__ inline size_t deq_table_bytes(int apieces, int n_books, int n_rows, int E) {
+  const size_t a = (((size_t)n_books * n_rows * 256 * 5 + (size_t)n_books * E) + 15) & ~(size_t)15;
+  return a + 4 * kMaxBooks + (apieces <= 2 ? (size_t)n_books * n_rows * 256 * 4 : 0);
+}
+
+__device__ inline DeqTables deq_tables_at(unsigned char *p, int n_books, int n_rows, int E) {
+  DeqTables t;
+  t.tv = reinterpret_cast<float *>(p);
+  t.tz = reinterpret_cast<uint8_t *>(t.tv + n_books * n_rows * 256);
+  t.rb = t.tz + n_books * n_rows * 256;
+  t.vmax = reinterpret_cast<float *>(p + ((((size_t)n_books * n_rows * 256 * 5 + (size_t)n_books * E) + 15) &
+                                          ~(size_t)15));
+  t.pq = reinterpret_cast<uint32_t *>(t.vmax + kMaxBooks);
+  return t;
+}
+
+// Stage the tables (ends with a workgroup barrier).  Zones above 2 read as 2
+// and rows past the table as its last row, so corrupt tables index nothing
+// outside LDS.
+template <int PREC>
+__device__ inline void stage_deq_tables(const DeqTables &t, const float *deq_val, const uint8_t *deq_zone,
+                                        const uint8_t *row_of_bin, int n_books, int n_rows, int E, int tid,
+                                        int nthreads) {
+  if (tid < kMaxBooks) t.vmax[tid] = 0.0f;
+  __syncthreads();
+  const int per_book = n_rows * 256;
+  for (int i = tid; i < n_books * per_book; i += nthreads) {
+    const float v = deq_val[i];
+    t.tv[i] = v;
+    const int z = deq_zone[i];
+    t.tz[i] = (uint8_t)(z < 2 ? z : 2);
+    note_table_max(t.vmax, i / per_book, v);
+  }
+  for (int i = tid; i < n_books * E; i += nthreads) {
+    const int r = row_of_bin[i];
+    t.rb[i] = (uint8_t)(r < n_rows ? r : n_rows - 1);
+  }
+  __syncthreads();
+  if constexpr (Traits<PREC>::kAPieces <= 2) stage_pieces<PREC>(t.pq, deq_val, t.vmax, per_book, n_books * per_book, tid, nthreads);
+  __syncthreads();
+}
+
+// The coefficient factors of a chunk of stream s in codebook `book`:
+// per-zone multipliers g0..g2 (the stream's scales, or 1, times 2^-e),
+// whether they differ from 1 (scaled), and the output factor oscale * 2^e.
+struct ChunkScales {
+  float g0, g1, g2, out;
+  bool scaled;
+};
+template <int PREC>
+__device__ inline ChunkScales chunk_scales(const float *gamma, float g0, float g1, float g2, float vmax_book,
+                                           float oscale) {
+  const float gm = gamma ? fmaxf(fabsf(g0), fmaxf(fabsf(g1), fabsf(g2))) : 1.0f;
+  const int e = coef_exp<PREC>(gamma ? vmax_book * gm : vmax_book);
+  const float f = pow2f(-e);
+  ChunkScales c;
+  c.g0 = gamma ? g0 * f : f;
+  c.g1 = gamma ? g1 * f : f;
+  c.g2 = gamma ? g2 * f : f;
+  c.scaled = gamma != nullptr || e != 0;
+  c.out = oscale * pow2f(e);
+  return c;
 }
 
 // Coefficient pieces of one k-step without per-stream scales: the 8 symbols
 // (s0, s1: byte j is bin k0 + j) looked up in the pre-split table of their
 // rows (pq: the book's table; rb: row of each bin when MULTI_ROW) and
 // repacked pairwise with byte permutes.  Returns whether any low piece is
-// nonzero.  Bins must lie inside [0, E) (E a multiple of 16).
-template <int PREC, bool MULTI_ROW>
+// nonzero.  Bins (k0 + KS j) must lie inside [0, E).
+template <int PREC, bool MULTI_ROW, int KS = 1>
 __device__ inline bool gather8(uint32_t s0, uint32_t s1, int k0, const uint32_t *pq, const uint8_t *rb,
                                u8v (&a)[Traits<PREC>::kAPieces]) {
   using T = Traits<PREC>;
@@ -142,7 +248,7 @@ __device__ inline bool gather8(uint32_t s0, uint32_t s1, int k0, const uint32_t 
 #pragma unroll
   for (int j = 0; j < 8; ++j) {
     const uint32_t sym = ((j < 4 ? s0 : s1) >> (8 * (j & 3))) & 255u;
-    const uint32_t row = MULTI_ROW ? (uint32_t)rb[k0 + j] : 0u;
+    const uint32_t row = MULTI_ROW ? (uint32_t)rb[k0 + KS * j] : 0u;
     t[j] = pq[row * 256 + sym];
   }
   uint32_t hi[4], lo[4];
@@ -282,12 +388,13 @@ __device__ inline void contract_dequant(f16v (&acc)[NT], const unsigned char *sb
 }
 
 // Contract a tile with the form that applies and hand the result to emit
-// (each form keeps its own accumulators up to the stores).
+// (each form keeps its own accumulators up to the stores).  Without per-stream
+// scales the pre-split table already holds the book's coefficient factor.
 template <int PREC, int NT, typename Emit>
 __device__ inline void tile_contract_emit(const unsigned char *sb, int base, int h, int col, int S, int E, bool valid,
                                           const uint16_t *Bs, int RS, const uint8_t *rb, const float *tv,
                                           const uint8_t *tz, const uint32_t *pq, int n_rows, const float *gamma,
-                                          float g0, float g1, float g2, Emit &&emit) {
+                                          const ChunkScales &cs, Emit &&emit) {
   if constexpr (Traits<PREC>::kAPieces <= 2) {
     if (!gamma && (E % 16) == 0) {
       if (n_rows > 1) {
@@ -303,7 +410,7 @@ __device__ inline void tile_contract_emit(const unsigned char *sb, int base, int
     }
   }
   f16v acc[NT];
-  contract_dequant<PREC, NT>(acc, sb, base, h, col, S, E, valid, Bs, RS, rb, tv, tz, gamma != nullptr, g0, g1, g2);
+  contract_dequant<PREC, NT>(acc, sb, base, h, col, S, E, valid, Bs, RS, rb, tv, tz, cs.scaled, cs.g0, cs.g1, cs.g2);
   emit(acc);
 }
 

@@ -66,6 +66,12 @@ _SIGS = {
                                                ctypes.c_size_t, _vp, ctypes.c_int32, _vp, _vp, _vp]),
     "fptc_dequant_idct_backward": (ctypes.c_int32, [_P(fptc_batch), _P(fptc_codec), _P(fptc_launch), _vp,
                                                     ctypes.c_size_t, _vp, _vp, _vp, _vp, _vp]),
+    "fptc_quantize_batch": (ctypes.c_int32, [_P(fptc_batch), _P(fptc_quant_params), _vp, _vp, _vp, _vp, _vp, _vp]),
+    "fptc_histogram_batch": (ctypes.c_int32, [_P(fptc_batch), _vp, _vp, ctypes.c_int32, _vp, _vp]),
+    "fptc_percentile_workspace_size": (ctypes.c_size_t, []),
+    "fptc_abs_percentile": (ctypes.c_int32, [_vp, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                             ctypes.c_double, _vp, _vp, ctypes.c_size_t, _vp]),
+    "fptc_build_dct_table": (ctypes.c_int32, [ctypes.c_int32, ctypes.c_int32, _vp]),
     "fptc_build_lut": (ctypes.c_int32, [_vp, ctypes.c_int32, _vp]),
     "fptc_canonical_codes": (ctypes.c_int32, [_vp, _vp]),
     "fptc_code_lengths": (ctypes.c_int32, [_vp, ctypes.c_int32, _vp]),
@@ -190,7 +196,35 @@ def fptc_decompress_batch(batch, codec, launch, ws, gamma, precision, out, statu
                                                                  _stream(stream)))
 
 
+def fptc_quantize_batch(batch, q, dct_table, sym_off, x, symbols_out, coef_out=None, stream=None):
+    _check("fptc_quantize_batch", load().fptc_quantize_batch(ctypes.byref(batch), ctypes.byref(q), _ptr(dct_table),
+                                                             _ptr(sym_off), _ptr(x), _ptr(symbols_out),
+                                                             _ptr(coef_out), _stream(stream)))
+
+
+def fptc_histogram_batch(batch, sym_off, symbols, n_books, counts, stream=None):
+    _check("fptc_histogram_batch", load().fptc_histogram_batch(ctypes.byref(batch), _ptr(sym_off), _ptr(symbols),
+                                                               int(n_books), _ptr(counts), _stream(stream)))
+
+
+def fptc_percentile_workspace_size() -> int:
+    return int(load().fptc_percentile_workspace_size())
+
+
+def fptc_abs_percentile(coef, n_windows, E, k0, k1, p, out, ws, stream=None):
+    _check("fptc_abs_percentile", load().fptc_abs_percentile(_ptr(coef), int(n_windows), int(E), int(k0), int(k1),
+                                                             float(p), _ptr(out), _ptr(ws),
+                                                             ws.numel() * ws.element_size(), _stream(stream)))
+
+
 # ------------------------------------------------------------ host calls
+
+
+def fptc_build_dct_table(N: int, E: int) -> np.ndarray:
+    t = np.zeros((E, N + 1), dtype=np.float64)
+    _check("fptc_build_dct_table", load().fptc_build_dct_table(int(N), int(E), _ptr(t)))
+    return t
+
 
 
 def fptc_build_lut(code_len: np.ndarray, lmax: int) -> np.ndarray:

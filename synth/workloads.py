@@ -12,6 +12,10 @@ take their inputs from here, so they decode the same streams.
   grad       256 streams of 2^18 samples, power-grid and meteorological 50/50
   large      64 channels of 2^24 EEG-like samples mixed by a 64 x 64 matrix
              with N(0, 1/64) entries
+  paper      256 streams of 2^20 EEG-like samples (the paper's operating
+             point is quoted on biomedical recordings)
+  sweep      128 streams of 2^20 EEG-like samples, for the sweep over window
+             and kept coefficients
 """
 from __future__ import annotations
 
@@ -22,7 +26,7 @@ import numpy as np
 
 from .signals import DOMAINS, ROOT_SEED, batch_lengths, domain_signal, eeg_like, stream_rng, training_rng
 
-CONFIG_ID = {"plain": 0, "batch": 1, "precision": 2, "grad": 3, "large": 4}
+CONFIG_ID = {"plain": 0, "batch": 1, "precision": 2, "grad": 3, "large": 4, "paper": 5, "sweep": 6}
 
 
 @dataclass
@@ -61,6 +65,12 @@ def workload(name: str) -> Workload:
     elif name == "large":
         lens = np.full(64, 1 << 24, dtype=np.int64)
         dom = np.zeros(64, dtype=np.int64)
+    elif name == "paper":
+        lens = np.full(256, 1 << 20, dtype=np.int64)
+        dom = np.zeros(256, dtype=np.int64)
+    elif name == "sweep":
+        lens = np.full(128, 1 << 20, dtype=np.int64)
+        dom = np.zeros(128, dtype=np.int64)
     else:
         raise ValueError(f"unknown workload {name}")
     used = tuple(sorted(set(int(d) for d in dom)))

@@ -37,30 +37,34 @@ class Case:
                 np.concatenate([[0], np.cumsum(lens)]))
 
 
-def train_books(p: O.QuantParams, domains, config_id: int, n_train: int = 1 << 15):
+def train_books(p: O.QuantParams, domains, config_id: int, n_train: int = 1 << 15, amplitude: float = 1.0):
     books = []
     for d, dom in enumerate(domains):
-        tr = synth.domain_signal(dom, n_train, synth.training_rng(config_id, d)).astype(np.float32)
+        tr = (amplitude * synth.domain_signal(dom, n_train, synth.training_rng(config_id, d))).astype(np.float32)
         books.append(O.train_codebook(O.quantize_stream(tr, p)))
     return books
 
 
-def paper_params(N: int, E: int, domain: str, config_id: int, B1: int = 2, B2: int | None = None) -> O.QuantParams:
+def paper_params(N: int, E: int, domain: str, config_id: int, B1: int = 2, B2: int | None = None,
+                 amplitude: float = 1.0) -> O.QuantParams:
+    """Paper quantizer (mu = 50, alpha1 = 0.004) with A0 / A1 the 99.9th
+    percentiles of a training signal of the domain scaled by `amplitude`."""
     B2 = E // 2 if B2 is None else B2
     p = O.QuantParams("paper", N, E, B1=B1, B2=B2, mu=50.0, alpha1=0.004)
-    tr = synth.domain_signal(domain, 1 << 15, synth.training_rng(config_id, 99)).astype(np.float32)
+    tr = (amplitude * synth.domain_signal(domain, 1 << 15, synth.training_rng(config_id, 99))).astype(np.float32)
     p.A0, p.A1 = O.paper_zone_maxima(tr, p, 99.9)
     return p
 
 
 def build_case(p: O.QuantParams, domains, lengths, config_id: int, gamma=False, recon=True, threads: int = 8,
-               stream_domains=None) -> Case:
-    books = train_books(p, domains, config_id)
+               stream_domains=None, amplitude: float = 1.0) -> Case:
+    books = train_books(p, domains, config_id, amplitude=amplitude)
     n = len(lengths)
     sd = stream_domains if stream_domains is not None else [i % len(domains) for i in range(n)]
 
     def one(i):
-        x = synth.domain_signal(domains[sd[i]], int(lengths[i]), synth.stream_rng(config_id, i)).astype(np.float32)
+        x = (amplitude * synth.domain_signal(domains[sd[i]], int(lengths[i]),
+                                             synth.stream_rng(config_id, i))).astype(np.float32)
         w, sl, sym = O.encode_stream(x, p, books[sd[i]])
         return x, w, sl, sym
 

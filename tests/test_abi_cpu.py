@@ -194,3 +194,31 @@ def test_codec_tables_are_dense_row_major_per_book(O):
         assert np.array_equal(cd.lut.numpy().view(np.uint16)[b], F.fptc_build_lut(lens[b], 12))
     with pytest.raises(ValueError):
         F._ptr(np.zeros((4, 4))[:, ::2])
+
+
+@pytest.mark.parametrize("N", [4, 16, 64, 256])
+def test_dct_table_gives_the_oracle_transform_bit_for_bit(O, N):
+    # the table's cosines and scales, summed in n order with separately
+    # rounded products and sums (the GPU encoder's arithmetic), reproduce the
+    # oracle's FP64 DCT-II exactly; and the transform is the orthonormal one
+    import scipy.fft
+    tab = F.fptc_build_dct_table(N, N)
+    assert tab.shape == (N, N + 1)
+    rng = np.random.default_rng(N)
+    for _ in range(3):
+        x = rng.normal(0, 30, N).astype(np.float32).astype(np.float64)
+        got = np.empty(N)
+        for k in range(N):
+            s = 0.0
+            for n in range(N):
+                s = s + float(x[n]) * float(tab[k, n])
+            got[k] = float(tab[k, N]) * s
+        assert np.array_equal(got, O.dct_stream(x.astype(np.float32), N, N))
+        np.testing.assert_allclose(got, scipy.fft.dct(x, type=2, norm="ortho"), rtol=0, atol=1e-12 * np.abs(x).sum())
+
+
+def test_dct_table_rejects_bad_sizes():
+    with pytest.raises(F.FptcError):
+        F.fptc_build_dct_table(12, 4)
+    with pytest.raises(F.FptcError):
+        F.fptc_build_dct_table(64, 65)

@@ -56,3 +56,39 @@ def test_mfma_matches_fp32_path_bitwise_symbols():
     b = run_gpu(c, precision="fp16x2")
     assert np.array_equal(a["sym"], b["sym"])
     assert np.max(np.abs(a["out"] - b["out"])) <= 1e-5 * np.ptp(np.concatenate(c.recon))
+
+
+@pytest.mark.parametrize("fused", [False, True])
+@pytest.mark.parametrize("prec,tol", EXACT + [("fp16", 2e-3)])
+@pytest.mark.parametrize("amplitude", [3e4, 1e-4])
+@pytest.mark.parametrize("N,E", [(32, 16), (64, 64), (256, 256)])
+def test_fp16_range_of_large_and_tiny_coefficients(fused, prec, tol, amplitude, N, E):
+    # signals in units where the zone maxima A0 / A1 (and so the dequantized
+    # values) lie far above FP16's largest value 65504, or far below its
+    # normal range; per-zone scales on top
+    p = paper_params(N, E, "eeg", 1400 + N, amplitude=amplitude)
+    assert (max(p.A0, p.A1) > 1e5) == (amplitude > 1)
+    c = build_case(p, ["eeg", "seismic"], [N * 97 + 5, N * 40, 3 * N + 1], config_id=1400 + N, gamma=True,
+                   amplitude=amplitude)
+    res = run_gpu(c, precision=prec, fused=fused)
+    assert np.all(np.isfinite(res["out"]))
+    worst = check_parity(c, res, tol=tol, check_symbols=not fused)
+    print(f"{prec} fused={fused} N={N} amplitude={amplitude:g}: A0={p.A0:.3g} worst {worst:.3e}")
+
+
+@pytest.mark.parametrize("fused", [False, True])
+@pytest.mark.parametrize("prec,tol", [("fp32", 1e-5)] + EXACT)
+def test_paper_operating_point(fused, prec, tol):
+    # Table 1's typical values: N = 32, E = 16, B1 = 2, B2 = 16 (so the zero
+    # zone holds no kept bin), mu = 50, alpha1 = 0.004, zone maxima from the
+    # 99.9th percentile of |c| on training data of the domain
+    if fused and prec == "fp32":
+        pytest.skip("the fused path runs the MFMA precisions")
+    p = paper_params(32, 16, "eeg", 1500, B1=2, B2=16)
+    assert (p.N, p.E, p.B1, p.B2, p.mu, p.alpha1) == (32, 16, 2, 16, 50.0, 0.004)
+    rng = np.random.default_rng(1500)
+    lens = list(np.floor(2.0 ** rng.uniform(6, 15, size=14)).astype(int)) + [1, 31, 33, 32 * 64]
+    c = build_case(p, ["eeg", "seismic", "power", "meteo"], lens, config_id=1500)
+    res = run_gpu(c, precision=prec, fused=fused)
+    worst = check_parity(c, res, tol=tol, check_symbols=not fused)
+    print(f"Table 1 point, {prec} fused={fused}: worst range-relative error {worst:.3e}")
