@@ -100,7 +100,9 @@ typedef struct {
 typedef struct {
   int32_t N;                  /* window (DCT size): 4, 8, 16, 32, 64, 128 or 256 */
   int32_t E;                  /* kept coefficients per window, 1 <= E <= N (Section 3.1) */
-  int32_t lmax;               /* longest code, 1..12 (Section 3.3 length limit) */
+  int32_t lmax;               /* longest code, 1..16 (Section 3.3 length limit).  Above 12 the
+                                 kernels decode through two-level tables built in LDS from
+                                 lut; fptc_decompress_batch then supports N <= 128 only */
   int32_t n_books;            /* 1..8 */
   int32_t n_rows;             /* rows of the dequantization table, 1..4 */
   int32_t reserved0;

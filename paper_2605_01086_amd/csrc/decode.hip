@@ -33,11 +33,11 @@ __host__ __device__ inline size_t decode_wave_bytes(int wpc, int E) {
 __host__ __device__ inline size_t decode_lds(bool ms, int n_books, int lmax, int wpc, int E, int waves) {
   const size_t t = lut_lds_bytes(ms, n_books, lmax);
   const size_t need = t + (size_t)waves * decode_wave_bytes(wpc, E) + 16;
-  const size_t tmp = ms ? t + lut1_temp_bytes(n_books, lmax) : 0;
+  const size_t tmp = (ms && lmax <= kShortLmax) ? t + lut1_temp_bytes(n_books, lmax) : 0;
   return need > tmp ? need : tmp;
 }
 
-template <bool MS>
+template <bool MS, bool LG>
 __global__ void __launch_bounds__(1024) k_decode(const uint64_t *__restrict__ words, const uint8_t *__restrict__ symlen,
                                                  int n_streams, int64_t n_symbols, int E, int lmax, int n_books,
                                                  int wpc, const uint16_t *__restrict__ lut_g,
@@ -89,10 +89,11 @@ __global__ void __launch_bounds__(1024) k_decode(const uint64_t *__restrict__ wo
     const int mis = (int)(reinterpret_cast<uintptr_t>(dst) & 15);
     int err = 0;
     if (ok) {
-      const void *lb = MS ? (const void *)((const uint32_t *)lut + (book << lmax))
-                          : (const void *)((const uint16_t *)lut + (book << lmax));
-      err = decode_chunk<MS>(words, symlen, cm.first_word, cm.first_sym, nbytes, cm.word_end, cw, lb,
-                             cl + book * 256, MS ? binfo[book] : 0u, hs, buf + mis, lane);
+      const void *lb = LG   ? (const void *)((const uint16_t *)lut + (size_t)book * (kLongPrefixes + kLongSub))
+                       : MS ? (const void *)((const uint32_t *)lut + (book << lmax))
+                            : (const void *)((const uint16_t *)lut + (book << lmax));
+      err = decode_chunk<MS, kPreRounds, LG>(words, symlen, cm.first_word, cm.first_sym, nbytes, cm.word_end, cw, lb,
+                                             cl + book * 256, MS ? binfo[book] : 0u, hs, buf + mis, lane, lmax);
     }
     settle_chunk_words(nx);
     settle_lane(vm);
@@ -127,14 +128,14 @@ __global__ void __launch_bounds__(1024) k_decode(const uint64_t *__restrict__ wo
   }
 }
 
-template <bool MS>
+template <bool MS, bool LG>
 int launch_t(const fptc_batch &b, const fptc_codec &c, const Shape &s, const Plan &p, uint8_t *symbols,
              int32_t *status, void *stream) {
   const int threads = s.waves * kWave;
   const size_t lds = decode_lds(MS, c.n_books, c.lmax, s.wpc, c.E, s.waves);
   const int per_cu = (int)((160 * 1024) / lds);
   int blocks = s.blocks > 0 ? s.blocks : device_cu_count() * (per_cu < 1 ? 1 : (per_cu > 8 ? 8 : per_cu));
-  hipLaunchKernelGGL(k_decode<MS>, dim3(blocks), dim3(threads), lds, (hipStream_t)stream, b.words, b.symlen,
+  hipLaunchKernelGGL((k_decode<MS, LG>), dim3(blocks), dim3(threads), lds, (hipStream_t)stream, b.words, b.symlen,
                      b.n_streams, b.n_symbols, c.E, c.lmax, c.n_books, s.wpc, c.lut, p.hdr, p.chunk_meta, symbols,
                      status);
   return (int)hipGetLastError();
@@ -143,7 +144,7 @@ int launch_t(const fptc_batch &b, const fptc_codec &c, const Shape &s, const Pla
 }  // namespace
 
 int set_decode_attributes() {
-  return lds_attr(k_decode<true>) | lds_attr(k_decode<false>);
+  return lds_attr(k_decode<true, false>) | lds_attr(k_decode<false, false>) | lds_attr(k_decode<false, true>);
 }
 
 // The smaller (single-symbol) layout: what the launch needs at least.
@@ -153,9 +154,10 @@ size_t decode_lds_bytes(const fptc_codec &c, const Shape &s) {
 
 int launch_decode(const fptc_batch &b, const fptc_codec &c, const Shape &s, const Plan &p, uint8_t *symbols,
                   int32_t *status, void *stream) {
+  if (c.lmax > kShortLmax) return launch_t<false, true>(b, c, s, p, symbols, status, stream);
   if (decode_lds(true, c.n_books, c.lmax, s.wpc, c.E, s.waves) <= 160 * 1024)
-    return launch_t<true>(b, c, s, p, symbols, status, stream);
-  return launch_t<false>(b, c, s, p, symbols, status, stream);
+    return launch_t<true, false>(b, c, s, p, symbols, status, stream);
+  return launch_t<false, false>(b, c, s, p, symbols, status, stream);
 }
 
 }  // namespace fptc

@@ -31,6 +31,15 @@
 //    offsets are at most 14).  Writes past a lane's run are suppressed, so no
 //    fix-up is needed.  A per-codebook info word records the form chosen:
 //      bit 0 sparse, bits 8..15 F, bits 16..23 code length of F.
+//  * two-level (uint16), for codes longer than kShortLmax = 12 bits (the
+//    2^lmax-entry table of Section 3.3 would not fit in LDS): a primary table
+//    indexed by the first 12 bits of the peek holds the single-symbol entry
+//    of every code of at most 12 bits; a 12-bit prefix that starts longer
+//    codes holds bit 15, its sub-table's offset (bits 0..11) and index width
+//    d - 1 (bits 12..14, d = its longest code's length - 12), and the sub-table
+//    entry for the next d bits of the peek is the code's single-symbol entry.
+//    At most 256 prefixes start longer codes (each holds a symbol), so the
+//    sub-tables never exceed 256 * 16 entries; 16 KB per codebook in all.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -48,8 +57,14 @@ constexpr int kSymPrefix = 64;
 constexpr int kPreRounds = 2;
 constexpr uint32_t kLutMissing = 1u << 30;
 
-// multi-symbol: entries | code lengths [book][256] | info word per book
+constexpr int kShortLmax = 12;  // longest code the one-level tables cover
+constexpr int kLongPrefixes = 1 << kShortLmax;
+constexpr int kLongSub = 256 * 16;  // sub-table entries per codebook, at most
+
+// multi-symbol: entries | code lengths [book][256] | info word per book;
+// codes longer than kShortLmax: the two-level tables (primary | sub) per book
 __host__ __device__ inline size_t lut_lds_bytes(bool ms, int n_books, int lmax) {
+  if (lmax > kShortLmax) return (size_t)n_books * (kLongPrefixes + kLongSub) * 2;
   const size_t e = (size_t)n_books << lmax;
   return ((ms ? e * 4 + (size_t)n_books * 260 : e * 2) + 15) & ~(size_t)15;
 }
@@ -145,12 +160,82 @@ __device__ inline void build_lut3(uint32_t *lut3, uint8_t *cl, uint32_t *info, c
   }
 }
 
+// An ABI table entry as a two-level table entry: lengths 0 (no code) and
+// above lmax (not a valid table) read as length 63, which overruns the word.
+__device__ inline uint16_t long_entry(uint16_t e, int lmax) {
+  const int l = e >> 8;
+  return (l >= 1 && l <= lmax) ? e : (uint16_t)((63u << 8) | (e & 0xffu));
+}
+// Longest valid code length among n ABI entries (0 if none).
+__device__ inline int longest_code(const uint16_t *__restrict__ L, int n, int lmax) {
+  int ml = 0;
+  for (int j = 0; j < n; ++j) {
+    const int l = L[j] >> 8;
+    if (l <= lmax) ml = max(ml, l);
+  }
+  return ml;
+}
+
+// Two-level tables of n_books codebooks from the ABI's 2^lmax-entry tables
+// (lmax > kShortLmax), one block: each thread sizes the sub-tables of a run
+// of prefixes, a block-wide scan places them, then each fills its own.
+// scan: LDS scratch of (blockDim / 64 + 1) ints.  Ends with a barrier.
+__device__ inline void build_long_tables(uint16_t *tab, const uint16_t *__restrict__ lut_g, int lmax, int n_books,
+                                         int tid, int nthreads, int *scan) {
+  const int d = lmax - kShortLmax;
+  const int per = (kLongPrefixes + nthreads - 1) / nthreads;
+  const int lane = tid & 63, wid = tid >> 6;
+  for (int b = 0; b < n_books; ++b) {
+    const uint16_t *L = lut_g + ((size_t)b << lmax);
+    uint16_t *prim = tab + (size_t)b * (kLongPrefixes + kLongSub), *sub = prim + kLongPrefixes;
+    // longest code under each of this thread's prefixes (0: none longer than 12 bits)
+    int total = 0;
+    for (int i = 0; i < per; ++i) {
+      const int pfx = tid * per + i;
+      if (pfx >= kLongPrefixes) break;
+      const int ml = longest_code(L + ((size_t)pfx << d), 1 << d, lmax);
+      total += ml > kShortLmax ? 1 << (ml - kShortLmax) : 0;
+    }
+    // exclusive prefix of the totals over the block
+    const int incl = wave_incl_scan_dpp(total);
+    if (lane == 63) scan[wid] = incl;
+    __syncthreads();
+    int off = incl - total;
+    for (int w = 0; w < wid; ++w) off += scan[w];
+    __syncthreads();  // scan[] is read before the next book writes it
+    for (int i = 0; i < per; ++i) {
+      const int pfx = tid * per + i;
+      if (pfx >= kLongPrefixes) break;
+      const size_t base = (size_t)pfx << d;
+      const int ml = longest_code(L + base, 1 << d, lmax);
+      if (ml <= kShortLmax) {  // a code of at most 12 bits (or no code) covers the prefix
+        prim[pfx] = long_entry(L[base], lmax);
+        continue;
+      }
+      const int dp = ml - kShortLmax;
+      if (off + (1 << dp) > kLongSub) {  // cannot happen with 256 symbols; refuse the codes
+        prim[pfx] = (uint16_t)(63u << 8);
+        continue;
+      }
+      prim[pfx] = (uint16_t)(0x8000u | ((unsigned)(dp - 1) << 12) | (unsigned)off);
+      for (int j = 0; j < (1 << dp); ++j) sub[off + j] = long_entry(L[base + ((size_t)j << (d - dp))], lmax);
+      off += 1 << dp;
+    }
+  }
+  __syncthreads();
+}
+
 // Stage the lookup tables a decode kernel uses.  ms: multi-symbol tables at
 // lut (then the code lengths and the info words follow them); temp: LDS scratch of lut1_temp_bytes() that the
 // caller overwrites only after a barrier.  Ends with a block barrier.
 __device__ inline void stage_decode_tables(bool ms, unsigned char *lut, unsigned char *temp, const uint16_t *lut_g,
                                            int lmax, int n_books, int tid, int nthreads) {
   const int entries = n_books << lmax;
+  if (lmax > kShortLmax) {  // two-level tables; temp (at least 64 bytes) holds the scan
+    build_long_tables(reinterpret_cast<uint16_t *>(lut), lut_g, lmax, n_books, tid, nthreads,
+                      reinterpret_cast<int *>(temp));
+    return;
+  }
   if (ms) {
     uint16_t *t = reinterpret_cast<uint16_t *>(temp);
     for (int i = tid; i < entries; i += nthreads) t[i] = lut_g[i];
@@ -249,6 +334,29 @@ __device__ inline int decode_word(uint64_t wd, unsigned char *p, int cnt, const 
   return err;
 }
 
+// Two-level form of decode_word (codes up to lmax <= 16 bits): one primary
+// lookup per code, a second one for codes longer than kShortLmax bits.
+__device__ inline int decode_word_long(uint64_t wd, unsigned char *p, int cnt, const uint16_t *prim, int lmax,
+                                       int hs) {
+  unsigned char *const pe = p + cnt;
+  const int d = lmax - kShortLmax;
+  const uint16_t *sub = prim + kLongPrefixes;
+  int bits = 0;
+  do {
+    const uint32_t peek = (uint32_t)(wd >> 32) >> hs;
+    uint32_t e = prim[peek >> d];
+    if (e & 0x8000u) {
+      const int dp = (int)((e >> 12) & 7u) + 1;
+      e = sub[(e & 0xfffu) + ((peek & ((1u << d) - 1)) >> (d - dp))];
+    }
+    const int len = (int)((e >> 8) & 63u);
+    wd <<= len;
+    bits += len;
+    *p++ = (unsigned char)e;
+  } while (p < pe);
+  return bits > 64 ? FPTC_STREAM_OVERRUN : 0;
+}
+
 // Sparse-table form of decode_word: the buffer already holds the fill symbol
 // at every position; lf is the fill symbol's code length.  While 16 or more
 // symbols remain no entry can reach past the run, so the slot writes need no
@@ -306,9 +414,9 @@ __device__ inline void prefill_symbols(unsigned char *sb, int t_cnt, uint32_t fs
 // One round: 64 words, one per lane; a DPP prefix sum of symlen places each
 // lane's run at chunk-relative index o, and the lane decodes the run's part
 // inside [.., t_cnt).  P advances by the round's symbol count.
-template <bool MS>
+template <bool MS, bool LG = false>
 __device__ inline void decode_round(uint64_t word, int n, int &P, int t_cnt, const void *lut, const uint8_t *cl,
-                                    uint32_t binfo, int hs, unsigned char *sb, int &err) {
+                                    uint32_t binfo, int hs, unsigned char *sb, int &err, int lmax = 0) {
   if (n > 64) {
     err |= FPTC_STREAM_BAD_SYMLEN;
     n = 64;
@@ -318,7 +426,9 @@ __device__ inline void decode_round(uint64_t word, int n, int &P, int t_cnt, con
   const int o = P + incl - n;
   const int cnt = min(n, t_cnt - o);
   if (cnt > 0) {
-    if (MS && (binfo & 1u))
+    if constexpr (LG)
+      err |= decode_word_long(word, sb + o, cnt, reinterpret_cast<const uint16_t *>(lut), lmax, hs);
+    else if (MS && (binfo & 1u))
       err |= decode_word_sparse(word, sb + o, cnt, reinterpret_cast<const uint32_t *>(lut), cl, hs,
                                 (int)((binfo >> 16) & 255u));
     else
@@ -333,16 +443,17 @@ __device__ inline void decode_round(uint64_t word, int n, int &P, int t_cnt, con
 // cw holds the first PR rounds of words (load_chunk_words), later
 // rounds are loaded here one round ahead.  binfo: the codebook's info word
 // (multi-symbol tables; 0 otherwise).  Returns this lane's error bits.
-template <bool MS, int PR>
+template <bool MS, int PR, bool LG = false>
 __device__ inline int decode_chunk(const uint64_t *__restrict__ words, const uint8_t *__restrict__ symlen, int64_t fw,
                                    int p0, int t_cnt, int64_t wend, const ChunkWordsT<PR> &cw, const void *lut,
-                                   const uint8_t *cl, uint32_t binfo, int hs, unsigned char *sb, int lane) {
+                                   const uint8_t *cl, uint32_t binfo, int hs, unsigned char *sb, int lane,
+                                   int lmax = 0) {
   int err = 0, P = p0;
   if (MS && (binfo & 1u)) prefill_symbols(sb, t_cnt, (binfo >> 8) & 255u, lane);
   int64_t w = fw;
 #pragma unroll
   for (int r = 0; r < PR; ++r) {
-    if (P < t_cnt && w < wend) decode_round<MS>(cw.w[r], cw.n[r], P, t_cnt, lut, cl, binfo, hs, sb, err);
+    if (P < t_cnt && w < wend) decode_round<MS, LG>(cw.w[r], cw.n[r], P, t_cnt, lut, cl, binfo, hs, sb, err, lmax);
     w += 64;
   }
   if (P < t_cnt && w < wend) {
@@ -361,7 +472,7 @@ __device__ inline int decode_chunk(const uint64_t *__restrict__ words, const uin
         nword = words[w + 64 + lane];
         nn = symlen[w + 64 + lane];
       }
-      decode_round<MS>(word, n, P, t_cnt, lut, cl, binfo, hs, sb, err);
+      decode_round<MS, LG>(word, n, P, t_cnt, lut, cl, binfo, hs, sb, err, lmax);
       w += 64;
     }
   }

@@ -15,7 +15,7 @@ constexpr int kDefaultWavesPerBlock = 4;
 constexpr int kDefaultChunkGroup = 4;
 constexpr int kMaxBooks = 8;
 constexpr int kMaxRows = 4;
-constexpr int kMaxLmax = 12;
+constexpr int kMaxLmax = 16;  // codes above 12 bits decode through two-level tables
 constexpr int kTileWindows = 32;  // windows per MFMA tile (one 32x32 output block per wave)
 
 // Everything a wavefront needs to decode one chunk, written by the plan.

@@ -44,11 +44,11 @@ __host__ __device__ inline size_t fused_lds_bytes(bool ms, int bpieces, int N, i
   const size_t t = lut_lds_bytes(ms, n_books, lmax);
   const size_t need = t + (size_t)bpieces * N * (Kp + 8) * 2 + deq_table_bytes(bpieces, n_books, n_rows, E) +
                       (size_t)waves * fused_wave_bytes(E, wpc) + 16;
-  const size_t tmp = ms ? t + lut1_temp_bytes(n_books, lmax) : 0;
+  const size_t tmp = (ms && lmax <= kShortLmax) ? t + lut1_temp_bytes(n_books, lmax) : 0;
   return need > tmp ? need : tmp;
 }
 
-template <int PREC, int NT, bool MS>
+template <int PREC, int NT, bool MS, bool LG>
 __global__ void __launch_bounds__(64 * max_fused_waves(NT * 32)) k_fused(const uint64_t *__restrict__ words,
                                                             const uint8_t *__restrict__ symlen, int n_streams, int E,
                                                             int S, int lmax, int n_books, int n_rows, int wpc,
@@ -123,10 +123,12 @@ __global__ void __launch_bounds__(64 * max_fused_waves(NT * 32)) k_fused(const u
     // ---- 1. decode the chunk's symbols into sb[0 .. w_cnt * E)
     int err = 0;
     if (ok) {
-      const void *lb = MS ? (const void *)(reinterpret_cast<const uint32_t *>(lds) + (book << lmax))
-                          : (const void *)(reinterpret_cast<const uint16_t *>(lds) + (book << lmax));
-      err = decode_chunk<MS>(words, symlen, cm.first_word, cm.first_sym, w_cnt * E, cm.word_end, cw, lb,
-                             cl + book * 256, MS ? binfo[book] : 0u, hs, sb, lane);
+      const void *lb = LG   ? (const void *)(reinterpret_cast<const uint16_t *>(lds) +
+                                             (size_t)book * (kLongPrefixes + kLongSub))
+                       : MS ? (const void *)(reinterpret_cast<const uint32_t *>(lds) + (book << lmax))
+                            : (const void *)(reinterpret_cast<const uint16_t *>(lds) + (book << lmax));
+      err = decode_chunk<MS, kPreRounds, LG>(words, symlen, cm.first_word, cm.first_sym, w_cnt * E, cm.word_end, cw,
+                                             lb, cl + book * 256, MS ? binfo[book] : 0u, hs, sb, lane, lmax);
     }
     settle_chunk_words(nx);
     settle_lane(vm);
@@ -176,14 +178,14 @@ int pieces_of(int precision) {
   return precision == FPTC_BF16X3 ? 3 : (precision == FPTC_FP16X2 ? 2 : 1);
 }
 
-template <int PREC, int NT, bool MS>
+template <int PREC, int NT, bool MS, bool LG>
 int launch_t(const fptc_batch &b, const fptc_codec &c, const Shape &sh, const Plan &p, const float *gamma, float *out,
              int32_t *status, void *stream) {
   constexpr int N = NT * 32;
   const int S = (c.E + 15) / 16, Kp = S * 16;
   const size_t lds =
       fused_lds_bytes(MS, Traits<PREC>::kBPieces, N, c.E, Kp, sh.wpc, sh.waves, c.n_books, c.n_rows, c.lmax);
-  auto kern = k_fused<PREC, NT, MS>;
+  auto kern = k_fused<PREC, NT, MS, LG>;
   const int per_cu = (int)((160 * 1024) / lds);
   const int blocks = sh.blocks > 0 ? sh.blocks : device_cu_count() * (per_cu > 0 ? per_cu : 1);
   hipLaunchKernelGGL(kern, dim3(blocks), dim3(sh.waves * 64), lds, (hipStream_t)stream, b.words, b.symlen,
@@ -197,10 +199,11 @@ template <int PREC, int NT>
 int launch_ms(const fptc_batch &b, const fptc_codec &c, const Shape &sh, const Plan &p, const float *gamma,
               float *out, int32_t *status, void *stream) {
   const int Kp = (c.E + 15) / 16 * 16;
+  if (c.lmax > kShortLmax) return launch_t<PREC, NT, false, true>(b, c, sh, p, gamma, out, status, stream);
   if (fused_lds_bytes(true, Traits<PREC>::kBPieces, NT * 32, c.E, Kp, sh.wpc, sh.waves, c.n_books, c.n_rows,
                       c.lmax) <= 160 * 1024)
-    return launch_t<PREC, NT, true>(b, c, sh, p, gamma, out, status, stream);
-  return launch_t<PREC, NT, false>(b, c, sh, p, gamma, out, status, stream);
+    return launch_t<PREC, NT, true, false>(b, c, sh, p, gamma, out, status, stream);
+  return launch_t<PREC, NT, false, false>(b, c, sh, p, gamma, out, status, stream);
 }
 
 template <int PREC>
@@ -216,7 +219,8 @@ int launch_prec(const fptc_batch &b, const fptc_codec &c, const Shape &sh, const
 
 template <int PREC, int NT>
 int attrs_nt() {
-  return lds_attr(k_fused<PREC, NT, true>) | lds_attr(k_fused<PREC, NT, false>);
+  return lds_attr(k_fused<PREC, NT, true, false>) | lds_attr(k_fused<PREC, NT, false, false>) |
+         lds_attr(k_fused<PREC, NT, false, true>);
 }
 
 template <int PREC>

@@ -69,7 +69,7 @@ __host__ __device__ inline size_t w256_lds(bool fused, bool ms, int ap, int n_bo
   const size_t t = fused ? lut_lds_bytes(ms, n_books, lmax) : 0;
   const size_t need = t + a16(deq_table_bytes(ap, n_books, n_rows, E)) + kWaves256 * sizeof(Slot) +
                       (size_t)nxb * kWaves256 * kXchBytes + kWaves256 * wave256_bytes(wpc, E);
-  const size_t tmp = (fused && ms) ? t + lut1_temp_bytes(n_books, lmax) : 0;
+  const size_t tmp = (fused && ms && lmax <= kShortLmax) ? t + lut1_temp_bytes(n_books, lmax) : 0;
   return need > tmp ? need : tmp;
 }
 
@@ -264,7 +264,7 @@ __global__ void __launch_bounds__(kWaves256 * 64) k_w256(const uint64_t *__restr
       if (have) {
         const void *lb = MS ? (const void *)(reinterpret_cast<const uint32_t *>(lds) + (book << lmax))
                             : (const void *)(reinterpret_cast<const uint16_t *>(lds) + (book << lmax));
-        const int err = decode_chunk<MS, kPre256>(words, symlen, cm.first_word, cm.first_sym, cm.n_windows * E,
+        const int err = decode_chunk<MS, kPre256, false>(words, symlen, cm.first_word, cm.first_sym, cm.n_windows * E,
                                                   cm.word_end, cw, lb, cl + book * 256, MS ? binfo[book] : 0u, hs,
                                                   sb_own, lane);
         if (err && status) atomicOr(&status[s_id], err);
@@ -459,6 +459,7 @@ bool mfma256_supported(const fptc_codec &c, int precision, int wpc) {
 
 bool fused256_supported(const fptc_codec &c, int precision, int wpc, int waves) {
   if (precision < FPTC_FP16 || precision > FPTC_BF16X3 || waves != kWaves256) return false;
+  if (c.lmax > kShortLmax) return false;  // codes longer than 12 bits: decode, then dequant+IDCT
   if (c.E < 1 || c.E > N256) return false;
   return exchange_buffers(true, false, pieces(precision), c, wpc) > 0;
 }

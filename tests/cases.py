@@ -27,6 +27,7 @@ class Case:
     symbols: list          # oracle quantized symbols per stream
     gamma: np.ndarray = None
     recon: list = field(default_factory=list)
+    lmax: int = 12          # longest code of the codebooks
 
     def concat(self):
         lens = np.array([len(x) for x in self.signals], dtype=np.int64)

@@ -29,7 +29,7 @@ def run_gpu(case: Case, launch=None, precision="fp32", use_gamma=True, words_ove
         words = words_override
     if symlen_override is not None:
         symlen = symlen_override
-    codec = C.DeviceCodec(np.stack([b.lengths for b in case.books]), qparams(p), 12)
+    codec = C.DeviceCodec(np.stack([b.lengths for b in case.books]), qparams(p), case.lmax)
     batch = C.DeviceBatch(words, symlen, word_off, sample_off, p.N, p.E, case.book_id)
     L = launch or C.Launch()
     lc = L.c()

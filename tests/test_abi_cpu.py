@@ -35,18 +35,36 @@ def _trained_lengths(O, domain, N=64):
     return O.train_codebook(O.quantize_stream(x, p)).lengths
 
 
-@pytest.mark.parametrize("domain", ["eeg", "seismic", "power", "meteo"])
+@pytest.mark.parametrize("domain", ["eeg", "seismic", "power", "meteo", "long16"])
 def test_lut_matches_oracle_canonical_codes(O, domain):
-    lens = _trained_lengths(O, domain)
+    if domain == "long16":  # codes up to 16 bits
+        r = np.abs(np.arange(256) - 128).astype(np.float64)
+        lens, lmax = O.package_merge((1 + r ** 3).astype(np.uint64), 16), 16
+        assert lens.max() == 16
+    else:
+        lens, lmax = _trained_lengths(O, domain), 12
     codes = O.canonical_codes(lens)
     assert np.array_equal(F.fptc_canonical_codes(lens), codes)
-    lut = F.fptc_build_lut(lens, 12)
-    expect = np.zeros(4096, dtype=np.uint16)
+    lut = F.fptc_build_lut(lens, lmax)
+    expect = np.zeros(1 << lmax, dtype=np.uint16)
     for s in range(256):
         l = int(lens[s])
-        for tail in range(1 << (12 - l)):
-            expect[(int(codes[s]) << (12 - l)) | tail] = (l << 8) | s
+        for tail in range(1 << (lmax - l)):
+            expect[(int(codes[s]) << (lmax - l)) | tail] = (l << 8) | s
     assert np.array_equal(lut, expect)
+
+
+@pytest.mark.parametrize("lmax", [13, 14, 16])
+def test_code_lengths_at_long_limits_cost_the_oracle_optimum(O, lmax):
+    # length-limited optimum (package-merge) above 12 bits: same cost as the
+    # oracle's, Kraft equality, the limit reached
+    rng = np.random.default_rng(lmax)
+    freq = np.floor(2.0 ** rng.uniform(0, 30, 256)).astype(np.uint64)
+    ours = F.fptc_code_lengths(freq, lmax)
+    ref = O.package_merge(freq, lmax)
+    assert int(ours.max()) <= lmax and int(ref.max()) == lmax
+    assert sum(int(f) * int(l) for f, l in zip(freq, ours)) == sum(int(f) * int(l) for f, l in zip(freq, ref))
+    assert sum(1 << (lmax - int(l)) for l in ours if l) == 1 << lmax
 
 
 def test_lut_rejects_bad_lengths():
@@ -148,7 +166,7 @@ def test_argument_errors_return_before_any_launch():
         setattr(bb, field, bad)
         assert F.fptc_workspace_size(bb, cc, ll) == 0
         assert lib.fptc_plan_batch(by(bb), by(cc), by(ll), 16, 1 << 30, 16, None) == F.FPTC_ERR_INVALID_ARG
-    for field, bad in [("N", 3), ("N", 512), ("E", 0), ("E", 65), ("lmax", 13), ("n_books", 9), ("n_rows", 0),
+    for field, bad in [("N", 3), ("N", 512), ("E", 0), ("E", 65), ("lmax", 17), ("lmax", 0), ("n_books", 9), ("n_rows", 0),
                        ("lut", None), ("basis", None)]:
         bb, cc, ll = _fake_structs()
         setattr(cc, field, bad)
