@@ -221,6 +221,23 @@ FPTC_API int32_t fptc_decompress_batch(const fptc_batch *batch, const fptc_codec
                                        const void *ws, size_t ws_bytes, const float *gamma, int32_t precision,
                                        float *out, int32_t *stream_status, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops and harnesses that forbid allocation):
+ * fptc_plan_batch followed by fptc_decompress_batch, with the plan kept in a
+ * static device array of the library, FPTC_NOALLOC_WS_BYTES per device,
+ * reserved until the process ends, instead of a caller workspace.  The
+ * caller passes inputs and outputs only; the call allocates nothing.
+ * FPTC_ERR_WORKSPACE when the batch's plan needs more than that (compare
+ * fptc_workspace_size); other errors as fptc_decompress_batch, all before
+ * anything is enqueued.  Every call on a device uses that device's one
+ * array and rewrites all of the plan it reads: calls that overlap on one
+ * device (other streams, other host threads) race and must be ordered by
+ * the caller. */
+#define FPTC_NOALLOC_WS_BYTES (16u << 20)
+FPTC_API int32_t fptc_decompress_batch_noalloc(const fptc_batch *batch, const fptc_codec *codec,
+                                               const fptc_launch *launch, const float *gamma, int32_t precision,
+                                               float *out, int32_t *stream_status, void *stream);
+
 /* ------------------------------------------------ encode side (device calls)
  * The steps before the decode path: the encoder's transform and quantizer,
  * and the statistics a codebook and the paper quantizer are trained on.

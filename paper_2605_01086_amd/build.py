@@ -18,7 +18,7 @@ ROOT = os.path.dirname(HERE)
 OUT = os.path.join(HERE, "libfptc.so")
 BUILD = os.path.join(HERE, "_build")
 
-HIP_SOURCES = ["init.hip", "plan.hip", "decode.hip", "dqidct.hip", "dqidct_mfma.hip", "fused.hip", "mfma256.hip", "bwd.hip", "train.hip"]
+HIP_SOURCES = ["init.hip", "plan.hip", "decode.hip", "dqidct.hip", "dqidct_mfma.hip", "fused.hip", "mfma256.hip", "bwd.hip", "noalloc.hip", "train.hip"]
 HOST_SOURCES = ["abi.cpp", "host_tables.cpp"]
 
 ARCH = "gfx950"

@@ -22,7 +22,7 @@ std::vector<DeviceState> g_dev;
 int init_current_device() {
   (void)device_cu_count();  // cache the compute-unit count the launchers size grids by
   int rc = set_decode_attributes() | set_dqidct_mfma_attributes() | set_fused_attributes() |
-           set_mfma256_attributes() | set_bwd_attributes();
+           set_mfma256_attributes() | set_bwd_attributes() | (init_noalloc_scratch() ? 1 : 0);
   return rc ? (int)hipErrorInvalidValue : 0;
 }
 

@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(HERE, "libfptc.so")
 FPTC_OK, FPTC_ERR_INVALID_ARG, FPTC_ERR_UNSUPPORTED, FPTC_ERR_WORKSPACE, FPTC_ERR_HIP = range(5)
 FPTC_STREAM_BAD_COUNT, FPTC_STREAM_OVERRUN, FPTC_STREAM_BAD_SYMLEN, FPTC_STREAM_BAD_HEADER = 1, 2, 4, 8
 FPTC_FP32_SIMT, FPTC_FP16, FPTC_FP16X2, FPTC_BF16, FPTC_BF16X3 = range(5)
+FPTC_NOALLOC_WS_BYTES = 16 << 20  # static workspace of fptc_decompress_batch_noalloc, per device
 PRECISIONS = {"fp32": FPTC_FP32_SIMT, "fp16": FPTC_FP16, "fp16x2": FPTC_FP16X2, "bf16": FPTC_BF16,
               "bf16x3": FPTC_BF16X3}
 FPTC_QUANT_AMPLITUDE, FPTC_QUANT_PAPER = 0, 1
@@ -66,6 +67,8 @@ _SIGS = {
                                                ctypes.c_size_t, _vp, ctypes.c_int32, _vp, _vp, _vp]),
     "fptc_dequant_idct_backward": (ctypes.c_int32, [_P(fptc_batch), _P(fptc_codec), _P(fptc_launch), _vp,
                                                     ctypes.c_size_t, _vp, _vp, _vp, _vp, _vp]),
+    "fptc_decompress_batch_noalloc": (ctypes.c_int32, [_P(fptc_batch), _P(fptc_codec), _P(fptc_launch), _vp,
+                                                       ctypes.c_int32, _vp, _vp, _vp]),
     "fptc_quantize_batch": (ctypes.c_int32, [_P(fptc_batch), _P(fptc_quant_params), _vp, _vp, _vp, _vp, _vp, _vp]),
     "fptc_histogram_batch": (ctypes.c_int32, [_P(fptc_batch), _vp, _vp, ctypes.c_int32, _vp, _vp]),
     "fptc_percentile_workspace_size": (ctypes.c_size_t, []),
@@ -194,6 +197,14 @@ def fptc_decompress_batch(batch, codec, launch, ws, gamma, precision, out, statu
                                                                  ws.numel() * ws.element_size(), _ptr(gamma),
                                                                  int(precision), _ptr(out), _ptr(status),
                                                                  _stream(stream)))
+
+
+def fptc_decompress_batch_noalloc(batch, codec, launch, gamma, precision, out, status, stream=None):
+    if isinstance(precision, str):
+        precision = PRECISIONS[precision]
+    _check("fptc_decompress_batch_noalloc", load().fptc_decompress_batch_noalloc(
+        ctypes.byref(batch), ctypes.byref(codec), ctypes.byref(launch), _ptr(gamma), int(precision), _ptr(out),
+        _ptr(status), _stream(stream)))
 
 
 def fptc_quantize_batch(batch, q, dct_table, sym_off, x, symbols_out, coef_out=None, stream=None):
