@@ -35,11 +35,19 @@ constexpr int kWaves = kThreads / 64;
 
 __host__ __device__ constexpr size_t a16(size_t x) { return (x + 15) & ~(size_t)15; }
 
-// LDS bytes of one instantiation: basis pieces, tables, one 32-window symbol
-// tile per wave, the chunk counter (16 B).
+// Per-wave LDS: 16 bytes, one 32-window symbol tile, then (E < N) a staging
+// area for a quarter tile of output (8 N + 4 floats); with E = N the consumed
+// symbol tile holds it.
+__host__ __device__ constexpr size_t tile_sym_bytes(int E) { return a16((size_t)kTileWindows * E + 16); }
+__host__ __device__ constexpr size_t mfma_wave_bytes(int N, int E) {
+  return 16 + tile_sym_bytes(E) + (E < N ? a16((size_t)32 * N + 16) : 0);
+}
+
+// LDS bytes of one instantiation: basis pieces, tables, the waves' regions,
+// the chunk counter (16 B).
 __host__ __device__ constexpr size_t mfma_lds_bytes(int bpieces, int N, int Kp, int n_books, int n_rows, int E) {
   return (size_t)bpieces * N * (Kp + 8) * 2 + deq_table_bytes(bpieces, n_books, n_rows, E) +
-         (size_t)kWaves * (16 + a16((size_t)kTileWindows * E + 16)) + 16;
+         (size_t)kWaves * mfma_wave_bytes(N, E) + 16;
 }
 
 // The symbols of a 32-window tile, 16 bytes per lane per round: R rounds of
@@ -117,13 +125,13 @@ __global__ void __launch_bounds__(kThreads, NT >= 4 ? 2 : (NT == 2 ? 3 : 4)) k_d
   const float bscale = T::kF16 ? kBasisScaleF16 : 1.0f;
   stage_basis<PREC>(Bs, basis, N, E, Kp, RS, threadIdx.x, kThreads);
   stage_deq_tables<PREC>(dt, deq_val, deq_zone, row_of_bin, n_books, n_rows, E, threadIdx.x, kThreads);
-  unsigned *chunk_ctr = reinterpret_cast<unsigned *>(bufs + (size_t)kWaves * (16 + a16((size_t)kTileWindows * E + 16)));
+  unsigned *chunk_ctr = reinterpret_cast<unsigned *>(bufs + (size_t)kWaves * mfma_wave_bytes(N, E));
   if (threadIdx.x == 0) *chunk_ctr = 0;
   __syncthreads();
 
   const int lane = threadIdx.x & 63, col = lane & 31, h = lane >> 5;
   const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  unsigned char *sb = bufs + (size_t)wid * (16 + a16((size_t)kTileWindows * E + 16)) + 16;
+  unsigned char *sb = bufs + (size_t)wid * mfma_wave_bytes(N, E) + 16;
   const int64_t n_chunks = hdr[0];
   const int64_t cstride = (int64_t)gridDim.x * kWaves;
   const float oscale = 1.0f / bscale;
@@ -176,14 +184,12 @@ __global__ void __launch_bounds__(kThreads, NT >= 4 ? 2 : (NT == 2 ? 3 : 4)) k_d
           settle_lane(vm);
           settle_lane(vgn);
         }
-        if (E == N) {  // stage through the consumed symbol tile
+        {  // staged through LDS: the consumed symbol tile (E = N) or the wave's staging area
+          float *stage = E < N ? reinterpret_cast<float *>(sb + tile_sym_bytes(E)) : reinterpret_cast<float *>(sb) - 4;
           if (rem >= kTileWindows * N)
-            store_tile_whole<NT>(win0, acc, reinterpret_cast<float *>(sb) - 4, h, col, lane, cs.out);
+            store_tile_whole<NT>(win0, acc, stage, h, col, lane, cs.out);
           else
-            store_tile_staged<NT>(win0, acc, reinterpret_cast<float *>(sb) - 4, h, col, lane, rem, cs.out);
-        } else {
-#pragma unroll
-          for (int t = 0; t < NT; ++t) store_rows(win0, N, acc[t], t, h, col, rem, cs.out);
+            store_tile_staged<NT>(win0, acc, stage, h, col, lane, rem, cs.out);
         }
       };
       tile_contract_emit<PREC, NT>(sb, base, h, col, S, E, valid > 0, Bs, RS, dt.rb + book * E,

@@ -31,9 +31,11 @@ __host__ __device__ constexpr size_t align16(size_t x) { return (x + 15) & ~(siz
 __host__ __device__ constexpr int max_fused_waves(int N) { return N >= 128 ? 8 : 16; }
 
 // Per-wave LDS region: a prefix for symbols of the previous chunk, then the
-// chunk's decoded symbols.
-__host__ __device__ inline size_t fused_wave_bytes(int E, int wpc) {
-  return (size_t)kSymPrefix + align16((size_t)wpc * E + 16);
+// chunk's decoded symbols, then (E < N) a staging area for a quarter tile of
+// output (8 N + 4 floats), which with E = N fits in the consumed symbols.
+__host__ __device__ inline size_t fused_sym_bytes(int E, int wpc) { return align16((size_t)wpc * E + 16); }
+__host__ __device__ inline size_t fused_wave_bytes(int E, int wpc, int N) {
+  return (size_t)kSymPrefix + fused_sym_bytes(E, wpc) + (E < N ? align16((size_t)32 * N + 16) : 0);
 }
 
 // LDS: lookup tables | split basis | dequantization tables | wave buffers |
@@ -43,7 +45,7 @@ __host__ __device__ inline size_t fused_lds_bytes(bool ms, int bpieces, int N, i
                                                   int n_books, int n_rows, int lmax) {
   const size_t t = lut_lds_bytes(ms, n_books, lmax);
   const size_t need = t + (size_t)bpieces * N * (Kp + 8) * 2 + deq_table_bytes(bpieces, n_books, n_rows, E) +
-                      (size_t)waves * fused_wave_bytes(E, wpc) + 16;
+                      (size_t)waves * fused_wave_bytes(E, wpc, N) + 16;
   const size_t tmp = (ms && lmax <= kShortLmax) ? t + lut1_temp_bytes(n_books, lmax) : 0;
   return need > tmp ? need : tmp;
 }
@@ -77,13 +79,13 @@ __global__ void __launch_bounds__(64 * max_fused_waves(NT * 32)) k_fused(const u
   stage_decode_tables(MS, lds, lds + lut_bytes, lut_g, lmax, n_books, threadIdx.x, nthreads);
   stage_basis<PREC>(Bs, basis, N, E, Kp, RS, threadIdx.x, nthreads);
   stage_deq_tables<PREC>(dt, deq_val, deq_zone, row_of_bin, n_books, n_rows, E, threadIdx.x, nthreads);
-  unsigned *chunk_ctr = reinterpret_cast<unsigned *>(wave_base + (size_t)waves * fused_wave_bytes(E, wpc));
+  unsigned *chunk_ctr = reinterpret_cast<unsigned *>(wave_base + (size_t)waves * fused_wave_bytes(E, wpc, N));
   if (threadIdx.x == 0) *chunk_ctr = 0;
   __syncthreads();
 
   const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63, col = lane & 31, h = lane >> 5;
-  unsigned char *sb = wave_base + (size_t)wid * fused_wave_bytes(E, wpc) + kSymPrefix;
+  unsigned char *sb = wave_base + (size_t)wid * fused_wave_bytes(E, wpc, N) + kSymPrefix;
   const uint8_t *cl = lds + ((size_t)n_books << lmax) * 4;
   const uint32_t *binfo = reinterpret_cast<const uint32_t *>(cl + n_books * 256);  // multi-symbol form only
   const int hs = 32 - lmax;  // peek = top lmax bits of the word = hi32 >> hs
@@ -151,11 +153,13 @@ __global__ void __launch_bounds__(64 * max_fused_waves(NT * 32)) k_fused(const u
         float *win0 = out + cm.out_base + (int64_t)tt * kTileWindows * N;
         const int rem = cm.out_len - tt * kTileWindows * N;
         auto emit = [&](const f16v (&acc)[NT]) {
-          if (E == N && wpc >= kTileWindows) {  // a quarter tile fits in the consumed symbol buffer
+          if (E < N || wpc >= kTileWindows) {  // staged through LDS: E = N, the consumed symbols
+            float *stage = E < N ? reinterpret_cast<float *>(sb + fused_sym_bytes(E, wpc))
+                                 : reinterpret_cast<float *>(sb) - 4;
             if (rem >= kTileWindows * N)
-              store_tile_whole<NT>(win0, acc, reinterpret_cast<float *>(sb) - 4, h, col, lane, cs.out);
+              store_tile_whole<NT>(win0, acc, stage, h, col, lane, cs.out);
             else
-              store_tile_staged<NT>(win0, acc, reinterpret_cast<float *>(sb) - 4, h, col, lane, rem, cs.out);
+              store_tile_staged<NT>(win0, acc, stage, h, col, lane, rem, cs.out);
           } else {
 #pragma unroll
             for (int t = 0; t < NT; ++t) store_rows(win0, N, acc[t], t, h, col, rem, cs.out);

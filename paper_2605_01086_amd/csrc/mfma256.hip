@@ -472,8 +472,10 @@ __global__ void __launch_bounds__(kWaves256 * 64) k_w256(const uint64_t *__restr
 #pragma unroll
         for (int s2 = kMaxSteps - 1; s2 >= 0; --s2) {
           u8v a[AP];
+          a[0] = afrag[(p * kMaxSteps + s2) * 64 + lane];
 #pragma unroll
-          for (int q = 0; q < AP; ++q) a[q] = afrag[q * kFrags + (p * kMaxSteps + s2) * 64 + lane];
+          for (int q = 1; q < AP; ++q)  // lower pieces only when the tile has any
+            a[q] = rest ? afrag[q * kFrags + (p * kMaxSteps + s2) * 64 + lane] : u8v{};
           if (s2 & 1)
             a1 = mfma_pieces<PREC>(bv[s2], a, a1, AP > 1 && rest);
           else
