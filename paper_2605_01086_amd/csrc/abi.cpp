@@ -70,13 +70,8 @@ Layout layout_for(const fptc_batch *b, const fptc_codec *c, const Shape &s) {
   off = align256(off + L.seg_cap * sizeof(int32_t));
   L.seg_sum = off;
   off = align256(off + L.seg_cap * sizeof(int32_t));
-  L.seg_base = off;
-  off = align256(off + L.seg_cap * sizeof(int64_t));
   L.bwd_part = off;
   off = align256(off + L.chunk_cap * 3 * sizeof(double));
-  L.tile_cap = (max_windows + kTileWindows - 1) / kTileWindows + 1;
-  L.tile_stream = off;
-  off = align256(off + L.tile_cap * sizeof(int32_t));
   L.chunk_meta = off;
   off = align256(off + L.chunk_cap * sizeof(ChunkMeta));
   L.total = off;
@@ -90,14 +85,11 @@ Plan plan_view(void *ws, const Layout &L) {
   v.win_off = reinterpret_cast<int64_t *>(p + L.win_off);
   v.chunk_off = reinterpret_cast<int64_t *>(p + L.chunk_off);
   v.bwd_part = reinterpret_cast<double *>(p + L.bwd_part);
-  v.tile_stream = reinterpret_cast<int32_t *>(p + L.tile_stream);
   v.chunk_meta = reinterpret_cast<ChunkMeta *>(p + L.chunk_meta);
   v.seg_off = reinterpret_cast<int64_t *>(p + L.seg_off);
   v.seg_stream = reinterpret_cast<int32_t *>(p + L.seg_stream);
   v.seg_sum = reinterpret_cast<int32_t *>(p + L.seg_sum);
-  v.seg_base = reinterpret_cast<int64_t *>(p + L.seg_base);
   v.chunk_cap = L.chunk_cap;
-  v.tile_cap = L.tile_cap;
   v.seg_cap = L.seg_cap;
   return v;
 }

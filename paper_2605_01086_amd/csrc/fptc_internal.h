@@ -20,7 +20,7 @@ constexpr int kTileWindows = 32;  // windows per MFMA tile (one 32x32 output blo
 
 // Everything a wavefront needs to decode one chunk, written by the plan.
 struct ChunkMeta {
-  // written together, as one 16-byte group, by the plan's chunk-start pass
+  // the whole record is written once, by the plan's chunk-start pass
   int64_t first_word;  // global index of the first word holding a symbol of the chunk; -1 = skip
   int32_t first_sym;   // chunk-relative index of the first word's first symbol (<= 0)
   int32_t last;        // 1 for a stream's last chunk
@@ -48,15 +48,19 @@ struct Shape {
 };
 
 // Workspace layout of a plan.  Every section starts on a 256-byte boundary.
-//   hdr        int64[8]     [0] = chunk count, [1] = window count
+//   hdr        int64[8]     [0] = chunk count, [1] = window count,
+//                           [2] = segment count, [3] = segment capacity
 //   win_off    int64[n+1]   exclusive prefix of ceil(L_s / N)
-//   chunk_off  int64[n+1]   exclusive prefix of ceil(n_win_s / wpc) (0 for bad headers)
+//   chunk_off  int64[n+1]   exclusive prefix of ceil(n_win_s / wpc) (0 for streams
+//                           flagged by the stream pass)
+//   seg_off    int64[n+1]   exclusive prefix of each stream's symlen segments
+//   seg_stream int32[scap]  stream of each segment
+//   seg_sum    int32[scap]  symbols in each segment
 //   bwd_part   double[cap*3] backward partial sums per chunk and zone
-//   tile_stream int32[tcap] stream owning the first window of each 32-window tile
 //   chunk_meta ChunkMeta[cap] per-chunk decode record
 struct Layout {
-  size_t hdr, win_off, chunk_off, seg_off, bwd_part, tile_stream, seg_stream, seg_sum, seg_base, chunk_meta, total;
-  int64_t chunk_cap, tile_cap, seg_cap;
+  size_t hdr, win_off, chunk_off, seg_off, bwd_part, seg_stream, seg_sum, chunk_meta, total;
+  int64_t chunk_cap, seg_cap;
 };
 
 Layout layout_for(const fptc_batch *b, const fptc_codec *c, const Shape &s);
@@ -67,13 +71,11 @@ struct Plan {
   int64_t *win_off;
   int64_t *chunk_off;
   double *bwd_part;
-  int32_t *tile_stream;
   int64_t *seg_off;     // [n_streams + 1] symlen segments per stream, prefix
   int32_t *seg_stream;  // [seg_cap] stream of each segment
   int32_t *seg_sum;     // [seg_cap] symbols in each segment
-  int64_t *seg_base;    // [seg_cap] symbols of the stream before each segment
   ChunkMeta *chunk_meta;
-  int64_t chunk_cap, tile_cap, seg_cap;
+  int64_t chunk_cap, seg_cap;
 };
 
 Plan plan_view(void *ws, const Layout &L);

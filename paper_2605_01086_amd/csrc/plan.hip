@@ -2,9 +2,12 @@
 //
 // Section 4.2 places each word's decoded symbols by an exclusive prefix sum of
 // the per-word symbol counts.  Here the sum is taken per stream, in two levels
-// (4096-word segments, then the segments of each stream), and only the words
-// where a chunk of `wpc` windows begins are recorded: a chunk then decodes
-// from that word on its own, with no cross-chunk dependency.
+// (4096-word segments, then within a segment), and only the words where a
+// chunk of `wpc` windows begins are recorded: a chunk then decodes from that
+// word on its own, with no cross-chunk dependency.  Three launches: the
+// stream pass (one workgroup), the segment sums (one wavefront per segment)
+// and the chunk starts (one wavefront per segment, whose base is the sum of
+// the stream's earlier segments).
 #include <hip/hip_runtime.h>
 
 #include "fptc_internal.h"
@@ -20,9 +23,8 @@ constexpr int64_t kSegWords = 4096;  // words per segment
 // 16-byte symlen loads per lane): one-wave workgroups need no barrier in
 // their scan, and more of them fit on a CU at once, which is what a
 // latency-bound pass over many small segments needs.  The chunk-start pass
-// walks every word's symbol range, so it keeps 256 threads x 16 words.
+// has the same shape.
 constexpr int kSumThreads = kWave;
-constexpr int kChunkThreads = 256;
 
 // Inclusive scan across one 64-lane wavefront.
 template <typename T>
@@ -57,12 +59,16 @@ __device__ inline T block_excl_scan(T v, T *lds, T &total) {
   return r;
 }
 
-// One workgroup: per-stream window, chunk and symlen-segment counts, their
+// One workgroup: per-stream window, symlen-segment and chunk counts, their
 // exclusive prefix sums, header validation, and the segment -> stream map.
 // Segments are kSegWords words on a 16-word grid aligned down from the
-// stream's first word.  Each thread takes kStreamsPerThread consecutive
-// streams (all their offsets loaded at once), so a batch of up to
-// kPlanThreads * kStreamsPerThread streams needs one pass of block scans.
+// stream's first word.  A stream gets no chunks when its header is bad, when
+// it has windows but no words (its symbol count is wrong) or when its
+// segments do not fit the capacity (word ranges of streams overlap); it is
+// flagged, and nothing later reads its words.  Each thread takes
+// kStreamsPerThread consecutive streams (all their offsets loaded at once),
+// so a batch of up to kPlanThreads * kStreamsPerThread streams needs one pass
+// of block scans.
 constexpr int kStreamsPerThread = 4;
 
 __global__ void __launch_bounds__(kPlanThreads) k_plan_streams(fptc_batch b, int N, int E, int wpc,
@@ -103,42 +109,50 @@ __global__ void __launch_bounds__(kPlanThreads) k_plan_streams(fptc_batch b, int
     int64_t tot;
     int64_t w_at = carry_w + block_excl_scan<int64_t, kPlanThreads>(tw, lds, tot);
     carry_w += tot;
-    int64_t tc = 0, tg = 0;
+    int64_t tg = 0;
     int64_t wx[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       wx[k] = w_at;
       if (s0 + k < n && !flag[k] && w_at + nw[k] > win_cap) flag[k] = FPTC_STREAM_BAD_HEADER;
       w_at += nw[k];
-      nc[k] = flag[k] ? 0 : (nw[k] + wpc - 1) / wpc;
+      if (!flag[k] && nw[k] > 0 && wo[k + 1] <= wo[k]) flag[k] = FPTC_STREAM_BAD_COUNT;  // windows, no words
       const int64_t a0 = wo[k] & ~(int64_t)15;
-      ng[k] = (flag[k] || nc[k] == 0 || wo[k + 1] <= wo[k]) ? 0 : (wo[k + 1] - a0 + kSegWords - 1) / kSegWords;
-      tc += nc[k];
+      ng[k] = (flag[k] || nw[k] == 0) ? 0 : (wo[k + 1] - a0 + kSegWords - 1) / kSegWords;
       tg += ng[k];
+    }
+    int64_t g_at = carry_g + block_excl_scan<int64_t, kPlanThreads>(tg, lds, tot);
+    carry_g += tot;
+    const int64_t g_pass = carry_g - tot, g_tot = tot;  // this pass's first segment, its segments
+    int64_t tc = 0;
+    int64_t gx[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      gx[k] = g_at;
+      if (!flag[k] && g_at + ng[k] > seg_cap) flag[k] = FPTC_STREAM_BAD_HEADER;  // no segment room
+      g_at += ng[k];
+      nc[k] = flag[k] ? 0 : (nw[k] + wpc - 1) / wpc;
+      tc += nc[k];
     }
     int64_t c_at = carry_c + block_excl_scan<int64_t, kPlanThreads>(tc, lds, tot);
     carry_c += tot;
-    int64_t g_at = carry_g + block_excl_scan<int64_t, kPlanThreads>(tg, lds, tot);
-    carry_g += tot;
-    const int64_t g_pass = carry_g - tot;  // this pass's first segment
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       const int s = s0 + k;
       if (s < n) {
         win_off[s] = wx[k];
         chunk_off[s] = c_at;
-        seg_off[s] = g_at;
+        seg_off[s] = gx[k];
         if (status) status[s] = flag[k];
       }
-      seg_at[threadIdx.x * K + k] = g_at;  // past n: the pass's end
+      seg_at[threadIdx.x * K + k] = gx[k];  // past n: the pass's end
       c_at += nc[k];
-      g_at += ng[k];
     }
     if (threadIdx.x == 0) seg_at[kPlanThreads * K] = carry_g;
     __syncthreads();
     // segment -> stream map: each thread a contiguous range of this pass's
     // segments, its first stream by binary search, then walking forward
-    const int64_t per = (tot + kPlanThreads - 1) / kPlanThreads;
+    const int64_t per = (g_tot + kPlanThreads - 1) / kPlanThreads;
     const int64_t g_lo = g_pass + (int64_t)threadIdx.x * per, g_hi = min(g_lo + per, carry_g);
     if (g_lo < g_hi) {
       int lo = 0, hi = kPlanThreads * K - 1;  // last local stream whose first segment is <= g_lo
@@ -264,26 +278,6 @@ __device__ inline int seg_words_sum(const SegWords<WPT> &sw) {
   return (int)sum;
 }
 
-// Exclusive block scan of int values (kChunkThreads threads) with DPP wave
-// scans; returns the exclusive prefix and the block total.
-__device__ inline int block_excl_scan_dpp(int v, int *lds, int &total) {
-  const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
-  constexpr int NW = kChunkThreads / kWave;
-  const int incl = wave_incl_scan_dpp(v);
-  if (lane == kWave - 1) lds[wid] = incl;
-  __syncthreads();
-  int before = 0, tot = 0;
-#pragma unroll
-  for (int i = 0; i < NW; ++i) {
-    const int x = lds[i];
-    before += i < wid ? x : 0;
-    tot += x;
-  }
-  __syncthreads();
-  total = tot;
-  return before + incl - v;
-}
-
 // Exclusive scan across the segment's one wavefront; total = the wave's sum.
 __device__ inline int seg_excl_scan(int v, int &total) {
   const int incl = wave_incl_scan_dpp(v);
@@ -314,114 +308,142 @@ __global__ void __launch_bounds__(kSumThreads) k_plan_seg_sums(fptc_batch b, con
   if (bad && status) atomicOr(&status[s], bad);
 }
 
-// One workgroup per stream: exclusive scan of its segment sums (symbols of
-// the stream before each segment), the symbol-count check, the chunk
-// records' fixed fields, and the 32-window tile owners.
-__global__ void __launch_bounds__(kScanThreads) k_plan_stream_scan(fptc_batch b, int N, int E, int wpc,
-                                                                   const int64_t *win_off, const int64_t *chunk_off,
-                                                                   const int64_t *seg_off, int64_t seg_cap,
-                                                                   const int32_t *seg_sum, int64_t *seg_base,
-                                                                   int32_t *tile_stream,
-                                                                   int64_t tile_cap, ChunkMeta *meta,
-                                                                   int32_t *status) {
-  __shared__ int64_t lds[kScanThreads / kWave + 1];
-  const int s = blockIdx.x;
-  // everything of the stream at once: one round trip before any use
-  const int64_t wo0 = win_off[s], wo1 = win_off[s + 1];
-  const int64_t c0 = chunk_off[s], nc = chunk_off[s + 1] - c0;
-  const int64_t w1 = b.word_off[s + 1];
-  const int64_t so = b.sample_off[s], L = b.sample_off[s + 1] - so;
-  const int64_t g0 = seg_off[s], g1 = seg_off[s + 1];
-  pin(wo0), pin(wo1), pin(c0), pin(nc), pin(w1), pin(so), pin(L), pin(g0), pin(g1);
-  // Every stream, valid or not, records itself as the owner of the 32-window
-  // tiles whose first window it holds, so a tile's first stream is one load.
-  {
-    const int64_t t0 = (wo0 + kTileWindows - 1) / kTileWindows;
-    const int64_t t1 = (wo1 + kTileWindows - 1) / kTileWindows;
-    for (int64_t t = t0 + threadIdx.x; t < t1 && t < tile_cap; t += kScanThreads) tile_stream[t] = s;
-  }
-  if (nc <= 0) return;  // empty stream or bad header (then status already flagged)
-  const int64_t nw = wo1 - wo0;
-  {
-    const int bk = b.book_id ? (int)b.book_id[s] : 0;
-    for (int64_t i = threadIdx.x; i < nc; i += kScanThreads) {
-      ChunkMeta cm;
-      const int64_t wb = i * wpc;
-      const int64_t nwc = nw - wb < wpc ? nw - wb : wpc;
-      const int64_t ol = L - wb * N < nwc * N ? L - wb * N : nwc * N;
-      cm.first_word = -1;
-      cm.first_sym = 0;
-      cm.last = i == nc - 1;
-      cm.word_end = w1;
-      cm.sym_base = wo0 * E + wb * E;
-      cm.out_base = so + wb * N;
-      cm.n_windows = (int32_t)nwc;
-      cm.out_len = (int32_t)ol;
-      cm.stream = s;
-      cm.book = bk;
-      cm.pad[0] = cm.pad[1] = 0;
-      meta[c0 + i] = cm;
-    }
-  }
-  const int64_t ng = g1 - g0;
-  if (g1 > seg_cap) {  // word ranges of streams overlap: no segment room
-    if (threadIdx.x == 0 && status) atomicOr(&status[s], FPTC_STREAM_BAD_HEADER);
-    return;  // its chunks keep first_word = -1
-  }
-  int64_t carry = 0;
-  for (int64_t base = 0; base < ng; base += kScanThreads) {
-    const int64_t i = base + threadIdx.x;
-    const int64_t v = i < ng ? seg_sum[g0 + i] : 0;
-    int64_t tot;
-    const int64_t ex = block_excl_scan<int64_t, kScanThreads>(v, lds, tot);
-    if (i < ng) seg_base[g0 + i] = carry + ex;
-    carry += tot;
-  }
-  if (threadIdx.x == 0 && carry != nw * E && status) atomicOr(&status[s], FPTC_STREAM_BAD_COUNT);
+// What the chunk records need of a stream.
+struct StreamChunks {
+  int64_t c0, nc;   // the stream's chunks
+  int64_t wo0, nw;  // its windows
+  int64_t so, L;    // its samples
+  int64_t w1;       // the end of its words
+  int s, book;
+};
+
+// Chunk m's whole record (Section 4.2's per-chunk offsets): where its words
+// start (first_word, or -1 when no word starts it) and its fixed fields.
+__device__ inline void put_record(ChunkMeta *meta, int64_t m, int64_t fw, int32_t fs, const StreamChunks &r, int N,
+                                  int E, int wpc) {
+  const int64_t wb = m * wpc;
+  const int64_t nwc = r.nw - wb < wpc ? r.nw - wb : wpc;
+  const int64_t ol = r.L - wb * N < nwc * N ? r.L - wb * N : nwc * N;
+  const int64_t sym_base = (r.wo0 + wb) * E, out_base = r.so + wb * N;
+  uint4 *d = reinterpret_cast<uint4 *>(meta + r.c0 + m);
+  d[0] = make_uint4((uint32_t)fw, (uint32_t)((uint64_t)fw >> 32), (uint32_t)fs, m == r.nc - 1 ? 1u : 0u);
+  d[1] = make_uint4((uint32_t)r.w1, (uint32_t)((uint64_t)r.w1 >> 32), (uint32_t)sym_base,
+                    (uint32_t)((uint64_t)sym_base >> 32));
+  d[2] = make_uint4((uint32_t)out_base, (uint32_t)((uint64_t)out_base >> 32), (uint32_t)nwc, (uint32_t)ol);
+  d[3] = make_uint4((uint32_t)r.s, (uint32_t)r.book, 0u, 0u);
+}
+static_assert(offsetof(ChunkMeta, first_sym) == 8 && offsetof(ChunkMeta, last) == 12 &&
+                  offsetof(ChunkMeta, word_end) == 16 && offsetof(ChunkMeta, sym_base) == 24 &&
+                  offsetof(ChunkMeta, out_base) == 32 && offsetof(ChunkMeta, n_windows) == 40 &&
+                  offsetof(ChunkMeta, out_len) == 44 && offsetof(ChunkMeta, stream) == 48 &&
+                  offsetof(ChunkMeta, book) == 52,
+              "put_record writes ChunkMeta as four 16-byte groups");
+
+__device__ inline int64_t wave_sum64(int64_t v) {
+#pragma unroll
+  for (int d = kWave / 2; d >= 1; d >>= 1) v += __shfl_xor(v, d, kWave);
+  return v;
 }
 
-// One workgroup per segment: exclusive scan of its words' symlen on top of
-// the segment's base; every word whose symbol range [p, p + symlen) holds the
-// first symbol of a chunk (a multiple of wpc * E) becomes that chunk's first
-// word (the chunk before it ends at that word, inclusive when the chunk
-// starts inside the word).
-__global__ void __launch_bounds__(kChunkThreads) k_plan_seg_chunks(fptc_batch b, int E, int wpc, const int64_t *hdr,
+// One wavefront per segment.  Its base is the symbols of the stream's
+// earlier segments (their sums, added up); the chunks whose first symbol (a
+// multiple of wpc * E) falls in the segment are [m_lo, m_hi), one per lane in
+// turn, and each lane finds the word whose symbol range [p, p + symlen) holds
+// its chunk's first symbol: the lane of the segment by a binary search over
+// the lanes' exclusive prefixes, then the word among that lane's 64 counts,
+// both kept in LDS.  Consecutive lanes then write consecutive records.  The
+// stream's last segment also checks the stream's symbol count and writes the
+// records of the chunks no word starts (-1: skipped), which exist only when
+// the count is short; the two sets are disjoint, so every record is written
+// exactly once.
+__global__ void __launch_bounds__(kSumThreads) k_plan_seg_chunks(fptc_batch b, int N, int E, int wpc,
+                                                                  const int64_t *hdr, const int64_t *win_off,
                                                                   const int64_t *chunk_off, const int64_t *seg_off,
-                                                                  const int32_t *seg_stream,
-                                                                  const int64_t *seg_base, ChunkMeta *meta) {
+                                                                  const int32_t *seg_stream, const int32_t *seg_sum,
+                                                                  ChunkMeta *meta, int32_t *status) {
+  constexpr int WPT = kSegWords / kSumThreads;
+  __shared__ uint32_t counts[kSegWords / 4];  // lane l's packed counts at [l * WPT / 4, (l + 1) * WPT / 4)
+  __shared__ int lane_at[kWave + 1];          // exclusive prefix of the lanes' totals, then the total
   if (b.n_streams <= 0) return;
   const int64_t g = blockIdx.x;
+  const int lane = threadIdx.x;
   // as in k_plan_seg_sums: the stream index is clamped before any read with it
   const int s = clamp_stream(seg_stream[g], b.n_streams);
-  const int64_t gb = seg_base[g];
   const int64_t h2 = hdr[2], seg_cap = hdr[3];
   // everything of the stream at once: one round trip before the words
   const SegStream t = seg_stream_of(b, s, seg_off);
-  const int64_t c0 = chunk_off[s], nc = chunk_off[s + 1] - c0;
-  pin(t.w0), pin(t.w1), pin(t.g0), pin(t.g1), pin(h2), pin(seg_cap), pin(gb), pin(c0), pin(nc);
-  if (g >= h2 || t.g1 > seg_cap) return;  // past the plan, or the stream's segments did not fit (flagged)
-  constexpr int WPT = kSegWords / kChunkThreads;
-  __shared__ int lds[kChunkThreads / kWave];
+  StreamChunks r;
+  r.c0 = chunk_off[s];
+  r.nc = chunk_off[s + 1] - r.c0;
+  r.wo0 = win_off[s];
+  r.nw = win_off[s + 1] - r.wo0;
+  r.so = b.sample_off[s];
+  r.L = b.sample_off[s + 1] - r.so;
+  r.w1 = t.w1;
+  r.s = s;
+  r.book = b.book_id ? (int)b.book_id[s] : 0;
+  pin(t.w0), pin(t.w1), pin(t.g0), pin(t.g1), pin(h2), pin(seg_cap), pin(r.c0), pin(r.nc), pin(r.wo0), pin(r.nw),
+      pin(r.so), pin(r.L);
+  if (g >= h2 || t.g1 > seg_cap || r.nc <= 0) return;  // past the plan, or a stream without chunks
+  // the earlier segments' sums: at most a few per lane, loaded beside the words
+  int64_t before = 0;
+  {
+    const int64_t i0 = t.g0 + lane;
+    int32_t v0 = 0, v1 = 0, v2 = 0;
+    if (i0 < g) v0 = seg_sum[i0];
+    if (i0 + kWave < g) v1 = seg_sum[i0 + kWave];
+    if (i0 + 2 * kWave < g) v2 = seg_sum[i0 + 2 * kWave];
+    before = (int64_t)v0 + v1 + v2;
+    for (int64_t i = i0 + 3 * kWave; i < g; i += kWave) before += seg_sum[i];  // streams of > 192 segments
+  }
   SegWords<WPT> sw;
   load_seg_words(b, g, t, sw);
-  int tot;
-  const int ex = block_excl_scan_dpp(seg_words_sum(sw), lds, tot);
-  const int64_t cb = (int64_t)wpc * E;  // symbols per chunk
-  int64_t p = gb + ex;
-  // the boundaries inside this thread's words, from the first at or after p
-  int64_t m = (p + cb - 1) / cb;
-  int64_t mb = m * cb;
 #pragma unroll
-  for (int j = 0; j < WPT; ++j) {
-    const int c = sw.cnt(j);
-    for (; mb < p + c && m < nc; ++m, mb += cb) {
-      const int64_t w = sw.first + j;
-      // first word, first symbol and the last flag: one 16-byte store (the
-      // chunk before ends at this word, which its reader derives from these)
-      *reinterpret_cast<uint4 *>(meta + c0 + m) =
-          make_uint4((uint32_t)w, (uint32_t)((uint64_t)w >> 32), (uint32_t)(int32_t)(p - mb), m == nc - 1 ? 1u : 0u);
+  for (int q = 0; q < WPT / 16; ++q)
+    *reinterpret_cast<uint4 *>(&counts[lane * (WPT / 4) + 4 * q]) =
+        make_uint4(sw.x[4 * q], sw.x[4 * q + 1], sw.x[4 * q + 2], sw.x[4 * q + 3]);
+  int tot;
+  const int ex = seg_excl_scan(seg_words_sum(sw), tot);
+  lane_at[lane] = ex;
+  if (lane == 0) lane_at[kWave] = tot;
+  before = wave_sum64(before);
+  wave_sync_lds();
+  const int64_t cb = (int64_t)wpc * E;  // symbols per chunk
+  const int64_t m_lo = (before + cb - 1) / cb;
+  const int64_t m_end = (before + tot + cb - 1) / cb;
+  const int64_t m_hi = m_end < r.nc ? m_end : r.nc;
+  const int64_t first = sw.first - (int64_t)lane * WPT;  // the segment's first word
+  for (int64_t m = m_lo + lane; m < m_hi; m += kWave) {
+    const int at = (int)(m * cb - before);  // in [0, tot)
+    int lo = 0, hi = kWave - 1;             // the last lane whose prefix is <= at
+#pragma unroll
+    for (int step = 0; step < 6; ++step) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (lane_at[mid] <= at) lo = mid;
+      else hi = mid - 1;
     }
-    p += c;
+    int q = lane_at[lo], j = 0;
+    const uint32_t *cl = counts + lo * (WPT / 4);
+    uint32_t v = cl[0];
+    for (int d = 0; d < WPT / 4; ++d) {  // the dword, then the byte, holding symbol `at`
+      v = cl[d];
+      const int c4 = (int)__builtin_amdgcn_sad_u8(v, 0u, 0u);
+      j = 4 * d;
+      if (at < q + c4) break;
+      q += c4;
+    }
+    for (int k = 0; k < 3; ++k, ++j) {
+      const int c = (int)(v & 255u);
+      if (at < q + c) break;
+      q += c;
+      v >>= 8;
+    }
+    put_record(meta, m, first + (int64_t)lo * WPT + j, q - at, r, N, E, wpc);
+  }
+  if (g == t.g1 - 1) {
+    const int64_t total = before + tot;
+    if (lane == 0 && total != r.nw * E && status) atomicOr(&status[s], FPTC_STREAM_BAD_COUNT);
+    for (int64_t k = m_end + lane; k < r.nc; k += kWave) put_record(meta, k, -1, 0, r, N, E, wpc);
   }
 }
 
@@ -438,12 +460,8 @@ int launch_plan(const fptc_batch &b, const fptc_codec &c, const Shape &s, const 
   hipLaunchKernelGGL(k_plan_seg_sums, dim3(nseg), dim3(kSumThreads), 0, st, b, p.hdr, p.seg_off, p.seg_stream,
                      p.seg_sum, status);
   if ((e = hipGetLastError()) != hipSuccess) return (int)e;
-  hipLaunchKernelGGL(k_plan_stream_scan, dim3(b.n_streams), dim3(kScanThreads), 0, st, b, c.N, c.E, s.wpc,
-                     p.win_off, p.chunk_off, p.seg_off, p.seg_cap, p.seg_sum, p.seg_base, p.tile_stream, p.tile_cap,
-                     p.chunk_meta, status);
-  if ((e = hipGetLastError()) != hipSuccess) return (int)e;
-  hipLaunchKernelGGL(k_plan_seg_chunks, dim3(nseg), dim3(kChunkThreads), 0, st, b, c.E, s.wpc, p.hdr, p.chunk_off,
-                     p.seg_off, p.seg_stream, p.seg_base, p.chunk_meta);
+  hipLaunchKernelGGL(k_plan_seg_chunks, dim3(nseg), dim3(kSumThreads), 0, st, b, c.N, c.E, s.wpc, p.hdr, p.win_off,
+                     p.chunk_off, p.seg_off, p.seg_stream, p.seg_sum, p.chunk_meta, status);
   return (int)hipGetLastError();
 }
 
