@@ -59,6 +59,37 @@ __device__ inline T block_excl_scan(T v, T *lds, T &total) {
   return r;
 }
 
+// Exclusive block scan of two values at once (one set of barriers).
+template <int THREADS>
+__device__ inline void block_excl_scan2(int64_t a, int64_t b, int64_t *lds, int64_t &ea, int64_t &eb, int64_t &ta,
+                                        int64_t &tb) {
+  const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+  constexpr int NW = THREADS / kWave;
+  const int64_t ia = wave_incl_scan(a), ib = wave_incl_scan(b);
+  if (lane == kWave - 1) lds[wid] = ia, lds[NW + 1 + wid] = ib;
+  __syncthreads();
+  if (wid == 0) {
+    const int64_t x = lane < NW ? lds[lane] : 0, y = lane < NW ? lds[NW + 1 + lane] : 0;
+    const int64_t xi = wave_incl_scan(x), yi = wave_incl_scan(y);
+    if (lane < NW) lds[lane] = xi - x, lds[NW + 1 + lane] = yi - y;
+    if (lane == NW - 1) lds[NW] = xi, lds[2 * NW + 1] = yi;
+  }
+  __syncthreads();
+  ea = ia - a + lds[wid];
+  eb = ib - b + lds[NW + 1 + wid];
+  ta = lds[NW];
+  tb = lds[2 * NW + 1];
+  __syncthreads();
+}
+
+// ceil(a / d) for 0 <= a, 1 <= d: 32-bit division whenever the operands
+// allow (the 64-bit one is a long instruction sequence).
+__device__ inline int64_t ceil_div(int64_t a, int d) {
+  const uint64_t x = (uint64_t)a + (uint64_t)(d - 1);
+  if (x >> 32) return (int64_t)(x / (uint64_t)d);
+  return (int64_t)((uint32_t)x / (uint32_t)d);
+}
+
 // One workgroup: per-stream window, symlen-segment and chunk counts, their
 // exclusive prefix sums, header validation, and the segment -> stream map.
 // Segments are kSegWords words on a 16-word grid aligned down from the
@@ -75,7 +106,7 @@ __global__ void __launch_bounds__(kPlanThreads) k_plan_streams(fptc_batch b, int
                                                                int64_t *hdr, int64_t *win_off, int64_t *chunk_off,
                                                                int64_t *seg_off, int32_t *seg_stream,
                                                                int64_t seg_cap, int32_t *status) {
-  __shared__ int64_t lds[kPlanThreads / kWave + 1];
+  __shared__ int64_t lds[2 * (kPlanThreads / kWave + 1)];
   constexpr int K = kStreamsPerThread;
   __shared__ int64_t seg_at[kPlanThreads * K + 1];  // this pass's streams: first segment of each, then the end
   const int n = b.n_streams;
@@ -92,7 +123,7 @@ __global__ void __launch_bounds__(kPlanThreads) k_plan_streams(fptc_batch b, int
     }
     int64_t nw[K], nc[K], ng[K];
     int flag[K];
-    int64_t tw = 0;
+    int64_t tw = 0, tg = 0;
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       flag[k] = 0;
@@ -102,36 +133,34 @@ __global__ void __launch_bounds__(kPlanThreads) k_plan_streams(fptc_batch b, int
             wo[k + 1] > b.n_words)
           flag[k] = FPTC_STREAM_BAD_HEADER;
         else
-          nw[k] = (so[k + 1] - so[k] + N - 1) / N;
+          nw[k] = ceil_div(so[k + 1] - so[k], N);
       }
+      if (!flag[k] && nw[k] > 0 && wo[k + 1] <= wo[k]) flag[k] = FPTC_STREAM_BAD_COUNT;  // windows, no words
+      const int64_t a0 = wo[k] & ~(int64_t)15;
+      ng[k] = (flag[k] || nw[k] == 0) ? 0 : ceil_div(wo[k + 1] - a0, (int)kSegWords);
       tw += nw[k];
+      tg += ng[k];
     }
-    int64_t tot;
-    int64_t w_at = carry_w + block_excl_scan<int64_t, kPlanThreads>(tw, lds, tot);
+    int64_t w_at, g_at, tot, g_tot;
+    block_excl_scan2<kPlanThreads>(tw, tg, lds, w_at, g_at, tot, g_tot);
+    w_at += carry_w;
+    g_at += carry_g;
     carry_w += tot;
-    int64_t tg = 0;
-    int64_t wx[K];
+    const int64_t g_pass = carry_g;  // this pass's first segment
+    carry_g += g_tot;
+    int64_t tc = 0;
+    int64_t wx[K], gx[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       wx[k] = w_at;
-      if (s0 + k < n && !flag[k] && w_at + nw[k] > win_cap) flag[k] = FPTC_STREAM_BAD_HEADER;
-      w_at += nw[k];
-      if (!flag[k] && nw[k] > 0 && wo[k + 1] <= wo[k]) flag[k] = FPTC_STREAM_BAD_COUNT;  // windows, no words
-      const int64_t a0 = wo[k] & ~(int64_t)15;
-      ng[k] = (flag[k] || nw[k] == 0) ? 0 : (wo[k + 1] - a0 + kSegWords - 1) / kSegWords;
-      tg += ng[k];
-    }
-    int64_t g_at = carry_g + block_excl_scan<int64_t, kPlanThreads>(tg, lds, tot);
-    carry_g += tot;
-    const int64_t g_pass = carry_g - tot, g_tot = tot;  // this pass's first segment, its segments
-    int64_t tc = 0;
-    int64_t gx[K];
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
       gx[k] = g_at;
-      if (!flag[k] && g_at + ng[k] > seg_cap) flag[k] = FPTC_STREAM_BAD_HEADER;  // no segment room
+      // windows past the batch's capacity, or segments past theirs (word
+      // ranges of streams overlap): a bad header, which takes precedence
+      if (s0 + k < n && !(flag[k] & FPTC_STREAM_BAD_HEADER) && (w_at + nw[k] > win_cap || g_at + ng[k] > seg_cap))
+        flag[k] = FPTC_STREAM_BAD_HEADER;
+      w_at += nw[k];
       g_at += ng[k];
-      nc[k] = flag[k] ? 0 : (nw[k] + wpc - 1) / wpc;
+      nc[k] = flag[k] ? 0 : ceil_div(nw[k], wpc);
       tc += nc[k];
     }
     int64_t c_at = carry_c + block_excl_scan<int64_t, kPlanThreads>(tc, lds, tot);
@@ -286,10 +315,12 @@ __device__ inline int seg_excl_scan(int v, int &total) {
 }
 
 // One wavefront per segment: the segment's symbol count (symlen clamped to
-// 64; a larger symlen is flagged).
+// 64; a larger symlen is flagged).  Segments of streams without chunks
+// (flagged by the stream pass) are skipped.
 __global__ void __launch_bounds__(kSumThreads) k_plan_seg_sums(fptc_batch b, const int64_t *hdr,
-                                                                const int64_t *seg_off, const int32_t *seg_stream,
-                                                                int32_t *seg_sum, int32_t *status) {
+                                                                const int64_t *chunk_off, const int64_t *seg_off,
+                                                                const int32_t *seg_stream, int32_t *seg_sum,
+                                                                int32_t *status) {
   if (b.n_streams <= 0) return;
   const int64_t g = blockIdx.x;
   // g < seg_cap, so this read is in bounds; past the plan's segments it may
@@ -298,8 +329,9 @@ __global__ void __launch_bounds__(kSumThreads) k_plan_seg_sums(fptc_batch b, con
   const int s = clamp_stream(seg_stream[g], b.n_streams);
   const int64_t h2 = hdr[2], seg_cap = hdr[3];
   const SegStream t = seg_stream_of(b, s, seg_off);
-  pin(t.w0), pin(t.w1), pin(t.g0), pin(t.g1), pin(h2), pin(seg_cap);
-  if (g >= h2 || t.g1 > seg_cap) return;  // past the plan, or the stream's segments did not fit (flagged)
+  const int64_t c0 = chunk_off[s], c1 = chunk_off[s + 1];
+  pin(t.w0), pin(t.w1), pin(t.g0), pin(t.g1), pin(h2), pin(seg_cap), pin(c0), pin(c1);
+  if (g >= h2 || t.g1 > seg_cap || c1 <= c0) return;  // past the plan, or a stream without chunks
   SegWords<kSegWords / kSumThreads> sw;
   const int bad = load_seg_words(b, g, t, sw);
   int tot;
@@ -457,8 +489,8 @@ int launch_plan(const fptc_batch &b, const fptc_codec &c, const Shape &s, const 
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return (int)e;
   const unsigned nseg = (unsigned)(p.seg_cap > 0 ? p.seg_cap : 1);  // blocks past hdr[2] exit at once
-  hipLaunchKernelGGL(k_plan_seg_sums, dim3(nseg), dim3(kSumThreads), 0, st, b, p.hdr, p.seg_off, p.seg_stream,
-                     p.seg_sum, status);
+  hipLaunchKernelGGL(k_plan_seg_sums, dim3(nseg), dim3(kSumThreads), 0, st, b, p.hdr, p.chunk_off, p.seg_off,
+                     p.seg_stream, p.seg_sum, status);
   if ((e = hipGetLastError()) != hipSuccess) return (int)e;
   hipLaunchKernelGGL(k_plan_seg_chunks, dim3(nseg), dim3(kSumThreads), 0, st, b, c.N, c.E, s.wpc, p.hdr, p.win_off,
                      p.chunk_off, p.seg_off, p.seg_stream, p.seg_sum, p.chunk_meta, status);
