@@ -44,7 +44,7 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published peak
 MFMA_F16_PEAK_TFS = 2500.0  # MI355X dense FP16/BF16 matrix peak
 FP32_VEC_PEAK_TFS = 157.3  # MI355X FP32 vector peak
 STEP_F, STEP_C, THRESH = 0.25, 2.0, 16.0
-PLAN_KERNELS = "k_plan_streams+k_plan_seg_sums+k_plan_seg_chunks"
+PLAN_KERNELS = "k_plan_pass1+k_plan_seg_chunks"
 
 
 def log(msg: str) -> None:
@@ -296,7 +296,7 @@ def batched(s: Setup, launch, precision, fused, steps, warmup):
 
 def time_per_stream(s: Setup, launch, steps, precision):
     """The same decode issued as one plan/decode/dequant+IDCT call sequence per
-    stream: 3 calls and 5 kernels (3 plan kernels, decode, dequant+IDCT) each."""
+    stream: 3 calls and 4 kernels (2 plan kernels, decode, dequant+IDCT) each."""
     import ctypes
     import torch
     from paper_2605_01086_amd import fptc as F
@@ -638,7 +638,7 @@ def main():
             line["plain_per_stream_fp32"] = {"value": round(4 * s.n_samples / (ms_ps * 1e-3) / 1e9, 2),
                                              "unit": "GB/s", "ms_per_step": round(ms_ps, 3),
                                              "calls_per_step": 3 * s.batch.n_streams,
-                                             "kernels_per_step": 5 * s.batch.n_streams,
+                                             "kernels_per_step": 4 * s.batch.n_streams,
                                              "max_abs_diff_vs_batched_fp32_over_range": float(f"{rel:.3e}"),
                                              "batched_speedup": round(ms_ps / ms_step, 2)}
             del out_ps

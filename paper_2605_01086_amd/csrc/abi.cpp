@@ -63,13 +63,16 @@ Layout layout_for(const fptc_batch *b, const fptc_codec *c, const Shape &s) {
   off = align256(off + (n + 1) * sizeof(int64_t));
   L.seg_off = off;
   off = align256(off + (n + 1) * sizeof(int64_t));
-  // a stream's 4096-word segments start at its first word aligned down to 16:
-  // with disjoint word ranges at most (n_words + 16 n) / 4096 + n in all
-  L.seg_cap = (b->n_words + 16 * n) / 4096 + n + 1;
+  // a stream's pieces are the 4096-word segments of the batch its words
+  // touch: with disjoint word ranges at most n_words / 4096 + 2 n in all
+  L.seg_cap = b->n_words / 4096 + 2 * n + 1;
+  L.n_gseg = (b->n_words + 4095) / 4096;
   L.seg_stream = off;
   off = align256(off + L.seg_cap * sizeof(int32_t));
-  L.seg_sum = off;
-  off = align256(off + L.seg_cap * sizeof(int32_t));
+  L.gseg_sum = off;
+  off = align256(off + L.n_gseg * sizeof(int32_t));
+  L.gseg_lane = off;
+  off = align256(off + L.n_gseg * 64 * sizeof(int32_t));
   L.bwd_part = off;
   off = align256(off + L.chunk_cap * 3 * sizeof(double));
   L.chunk_meta = off;
@@ -88,9 +91,11 @@ Plan plan_view(void *ws, const Layout &L) {
   v.chunk_meta = reinterpret_cast<ChunkMeta *>(p + L.chunk_meta);
   v.seg_off = reinterpret_cast<int64_t *>(p + L.seg_off);
   v.seg_stream = reinterpret_cast<int32_t *>(p + L.seg_stream);
-  v.seg_sum = reinterpret_cast<int32_t *>(p + L.seg_sum);
+  v.gseg_sum = reinterpret_cast<int32_t *>(p + L.gseg_sum);
+  v.gseg_lane = reinterpret_cast<int32_t *>(p + L.gseg_lane);
   v.chunk_cap = L.chunk_cap;
   v.seg_cap = L.seg_cap;
+  v.n_gseg = L.n_gseg;
   return v;
 }
 

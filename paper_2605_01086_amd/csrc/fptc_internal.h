@@ -53,14 +53,15 @@ struct Shape {
 //   win_off    int64[n+1]   exclusive prefix of ceil(L_s / N)
 //   chunk_off  int64[n+1]   exclusive prefix of ceil(n_win_s / wpc) (0 for streams
 //                           flagged by the stream pass)
-//   seg_off    int64[n+1]   exclusive prefix of each stream's symlen segments
-//   seg_stream int32[scap]  stream of each segment
-//   seg_sum    int32[scap]  symbols in each segment
+//   seg_off    int64[n+1]   exclusive prefix of each stream's segment pieces
+//   seg_stream int32[scap]  stream of each piece
+//   gseg_sum   int32[nseg]  symbols of each 4096-word segment of the batch
+//   gseg_lane  int32[nseg*64] exclusive prefix of its 64-word blocks
 //   bwd_part   double[cap*3] backward partial sums per chunk and zone
 //   chunk_meta ChunkMeta[cap] per-chunk decode record
 struct Layout {
-  size_t hdr, win_off, chunk_off, seg_off, bwd_part, seg_stream, seg_sum, chunk_meta, total;
-  int64_t chunk_cap, seg_cap;
+  size_t hdr, win_off, chunk_off, seg_off, bwd_part, seg_stream, gseg_sum, gseg_lane, chunk_meta, total;
+  int64_t chunk_cap, seg_cap, n_gseg;
 };
 
 Layout layout_for(const fptc_batch *b, const fptc_codec *c, const Shape &s);
@@ -72,10 +73,11 @@ struct Plan {
   int64_t *chunk_off;
   double *bwd_part;
   int64_t *seg_off;     // [n_streams + 1] symlen segments per stream, prefix
-  int32_t *seg_stream;  // [seg_cap] stream of each segment
-  int32_t *seg_sum;     // [seg_cap] symbols in each segment
+  int32_t *seg_stream;  // [seg_cap] stream of each piece (a stream's words in one segment)
+  int32_t *gseg_sum;    // [n_gseg] symbols of each segment of the batch
+  int32_t *gseg_lane;   // [n_gseg * 64] exclusive prefix of each segment's 64-word blocks
   ChunkMeta *chunk_meta;
-  int64_t chunk_cap, seg_cap;
+  int64_t chunk_cap, seg_cap, n_gseg;
 };
 
 Plan plan_view(void *ws, const Layout &L);

@@ -1,13 +1,15 @@
 // Batch planning kernels (stream/chunk setup and the symlen prefix sums).
 //
 // Section 4.2 places each word's decoded symbols by an exclusive prefix sum of
-// the per-word symbol counts.  Here the sum is taken per stream, in two levels
-// (4096-word segments, then within a segment), and only the words where a
-// chunk of `wpc` windows begins are recorded: a chunk then decodes from that
-// word on its own, with no cross-chunk dependency.  Three launches: the
-// stream pass (one workgroup), the segment sums (one wavefront per segment)
-// and the chunk starts (one wavefront per segment, whose base is the sum of
-// the stream's earlier segments).
+// the per-word symbol counts.  Here the sum is taken in two levels over the
+// whole symlen array cut into 4096-word segments (each segment's total and
+// its 64-word partial prefixes), and a stream's symbols before any of its
+// words follow from those as differences; only the words where a chunk of
+// `wpc` windows begins are recorded: a chunk then decodes from that word on
+// its own, with no cross-chunk dependency.  Two launches: the stream pass
+// (one workgroup) beside the segment sums (one wavefront per segment), which
+// need nothing of each other, then the chunk starts (one wavefront per piece
+// of a stream in a segment).
 #include <hip/hip_runtime.h>
 
 #include "fptc_internal.h"
@@ -17,13 +19,11 @@ namespace fptc {
 namespace {
 
 constexpr int kPlanThreads = 1024;
-constexpr int kScanThreads = 256;
-constexpr int64_t kSegWords = 4096;  // words per segment
-// The segment sums take a segment per wavefront (64 lanes x 64 words, four
-// 16-byte symlen loads per lane): one-wave workgroups need no barrier in
-// their scan, and more of them fit on a CU at once, which is what a
-// latency-bound pass over many small segments needs.  The chunk-start pass
-// has the same shape.
+constexpr int64_t kSegWords = 4096;  // words per segment (a multiple of 64 x 64)
+constexpr int kSegShift = 12;
+static_assert(kSegWords == (int64_t)1 << kSegShift && kSegWords == kWave * 64, "segment geometry");
+// Every pass takes a segment (or a stream's piece of one) per wavefront:
+// 64 lanes x 64 words, four 16-byte symlen loads per lane, no barrier.
 constexpr int kSumThreads = kWave;
 
 // Inclusive scan across one 64-lane wavefront.
@@ -90,10 +90,10 @@ __device__ inline int64_t ceil_div(int64_t a, int d) {
   return (int64_t)((uint32_t)x / (uint32_t)d);
 }
 
-// One workgroup: per-stream window, symlen-segment and chunk counts, their
-// exclusive prefix sums, header validation, and the segment -> stream map.
-// Segments are kSegWords words on a 16-word grid aligned down from the
-// stream's first word.  A stream gets no chunks when its header is bad, when
+// One workgroup: per-stream window, segment-piece and chunk counts, their
+// exclusive prefix sums, header validation, and the piece -> stream map.  A
+// stream's pieces are the segments its words touch (segment k holds words
+// [kSegWords k, kSegWords (k + 1)) of the batch).  A stream gets no chunks when its header is bad, when
 // it has windows but no words (its symbol count is wrong) or when its
 // segments do not fit the capacity (word ranges of streams overlap); it is
 // flagged, and nothing later reads its words.  Each thread takes
@@ -102,10 +102,9 @@ __device__ inline int64_t ceil_div(int64_t a, int d) {
 // of block scans.
 constexpr int kStreamsPerThread = 4;
 
-__global__ void __launch_bounds__(kPlanThreads) k_plan_streams(fptc_batch b, int N, int E, int wpc,
-                                                               int64_t *hdr, int64_t *win_off, int64_t *chunk_off,
-                                                               int64_t *seg_off, int32_t *seg_stream,
-                                                               int64_t seg_cap, int32_t *status) {
+__device__ void stream_pass(const fptc_batch &b, int N, int E, int wpc, int64_t *hdr, int64_t *win_off,
+                            int64_t *chunk_off, int64_t *seg_off, int32_t *seg_stream, int64_t seg_cap,
+                            int32_t *status) {
   __shared__ int64_t lds[2 * (kPlanThreads / kWave + 1)];
   constexpr int K = kStreamsPerThread;
   __shared__ int64_t seg_at[kPlanThreads * K + 1];  // this pass's streams: first segment of each, then the end
@@ -136,7 +135,7 @@ __global__ void __launch_bounds__(kPlanThreads) k_plan_streams(fptc_batch b, int
           nw[k] = ceil_div(so[k + 1] - so[k], N);
       }
       if (!flag[k] && nw[k] > 0 && wo[k + 1] <= wo[k]) flag[k] = FPTC_STREAM_BAD_COUNT;  // windows, no words
-      const int64_t a0 = wo[k] & ~(int64_t)15;
+      const int64_t a0 = wo[k] & ~(kSegWords - 1);
       ng[k] = (flag[k] || nw[k] == 0) ? 0 : ceil_div(wo[k + 1] - a0, (int)kSegWords);
       tw += nw[k];
       tg += ng[k];
@@ -244,8 +243,8 @@ __device__ inline SegStream seg_stream_of(const fptc_batch &b, int s, const int6
 template <int WPT>
 __device__ inline int load_seg_words(const fptc_batch &b, int64_t g, const SegStream &t, SegWords<WPT> &sw) {
   static_assert(WPT % 16 == 0, "whole 16-byte symlen blocks per thread");
-  const int64_t a0 = t.w0 & ~(int64_t)15;
-  const int64_t first = a0 + (g - t.g0) * kSegWords + (int64_t)threadIdx.x * WPT;
+  const int64_t a0 = t.w0 & ~(kSegWords - 1);  // the stream's first segment
+  const int64_t first = a0 + (g - t.g0) * kSegWords + (int64_t)(threadIdx.x & (kWave - 1)) * WPT;
   sw.first = first;
   const bool aligned = (reinterpret_cast<uintptr_t>(b.symlen) & 15) == 0;
 #pragma unroll
@@ -314,30 +313,60 @@ __device__ inline int seg_excl_scan(int v, int &total) {
   return incl - v;
 }
 
-// One wavefront per segment: the segment's symbol count (symlen clamped to
-// 64; a larger symlen is flagged).  Segments of streams without chunks
-// (flagged by the stream pass) are skipped.
-__global__ void __launch_bounds__(kSumThreads) k_plan_seg_sums(fptc_batch b, const int64_t *hdr,
-                                                                const int64_t *chunk_off, const int64_t *seg_off,
-                                                                const int32_t *seg_stream, int32_t *seg_sum,
-                                                                int32_t *status) {
-  if (b.n_streams <= 0) return;
-  const int64_t g = blockIdx.x;
-  // g < seg_cap, so this read is in bounds; past the plan's segments it may
-  // hold anything, so it is clamped to a stream before the stream's offsets
-  // are read with it (such a block then returns on the header check)
-  const int s = clamp_stream(seg_stream[g], b.n_streams);
-  const int64_t h2 = hdr[2], seg_cap = hdr[3];
-  const SegStream t = seg_stream_of(b, s, seg_off);
-  const int64_t c0 = chunk_off[s], c1 = chunk_off[s + 1];
-  pin(t.w0), pin(t.w1), pin(t.g0), pin(t.g1), pin(h2), pin(seg_cap), pin(c0), pin(c1);
-  if (g >= h2 || t.g1 > seg_cap || c1 <= c0) return;  // past the plan, or a stream without chunks
-  SegWords<kSegWords / kSumThreads> sw;
-  const int bad = load_seg_words(b, g, t, sw);
-  int tot;
-  seg_excl_scan(seg_words_sum(sw), tot);  // only the wave's total is kept
-  if (threadIdx.x == 0) seg_sum[g] = tot;
-  if (bad && status) atomicOr(&status[s], bad);
+// Each byte of four packed symlen counts clamped to 64.
+__device__ inline uint32_t clamp64x4(uint32_t v) {
+  if (!((v & 0x80808080u) | (((v & 0x7f7f7f7fu) + 0x3f3f3f3fu) & 0x80808080u))) return v;
+  uint32_t c = 0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const uint32_t e = (v >> (8 * k)) & 255u;
+    c |= (e > 64u ? 64u : e) << (8 * k);
+  }
+  return c;
+}
+
+// One wavefront: segment G's symbol count and the exclusive prefix of its
+// 64-word blocks (symlen clamped to 64, as everywhere in the plan; the flag
+// for a larger one is raised where a stream's words are read).
+__device__ void segment_sums(const fptc_batch &b, int64_t G, int32_t *gseg_sum, int32_t *gseg_lane) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int64_t f0 = (G << kSegShift) + (int64_t)lane * 64;
+  const bool aligned = (reinterpret_cast<uintptr_t>(b.symlen) & 15) == 0;
+  uint32_t sum = 0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int64_t f = f0 + 16 * q;
+    uint32_t x[4] = {0u, 0u, 0u, 0u};
+    if (aligned && f + 16 <= b.n_words) {
+      const uint4 u = *reinterpret_cast<const uint4 *>(b.symlen + f);
+      x[0] = u.x, x[1] = u.y, x[2] = u.z, x[3] = u.w;
+    } else {
+#pragma unroll
+      for (int j = 0; j < 16; ++j)
+        if (f + j < b.n_words) x[j >> 2] |= (uint32_t)b.symlen[f + j] << (8 * (j & 3));
+    }
+#pragma unroll
+    for (int d = 0; d < 4; ++d) sum = __builtin_amdgcn_sad_u8(clamp64x4(x[d]), 0u, sum);
+  }
+  const int incl = wave_incl_scan_dpp((int)sum);
+  gseg_lane[(G << 6) + lane] = incl - (int)sum;
+  if (lane == kWave - 1) gseg_sum[G] = incl;
+}
+
+// The first launch: workgroup 0 runs the stream pass; every wavefront of the
+// others sums one segment.  The two need nothing of each other.
+constexpr int kSumWavesPerBlock = kPlanThreads / kWave;
+
+__global__ void __launch_bounds__(kPlanThreads) k_plan_pass1(fptc_batch b, int N, int E, int wpc, int64_t *hdr,
+                                                             int64_t *win_off, int64_t *chunk_off, int64_t *seg_off,
+                                                             int32_t *seg_stream, int64_t seg_cap, int32_t *gseg_sum,
+                                                             int32_t *gseg_lane, int64_t n_gseg, int32_t *status) {
+  if (blockIdx.x == 0) {
+    stream_pass(b, N, E, wpc, hdr, win_off, chunk_off, seg_off, seg_stream, seg_cap, status);
+    return;
+  }
+  const int64_t G = (int64_t)(blockIdx.x - 1) * kSumWavesPerBlock + (threadIdx.x >> 6);
+  if (G < n_gseg) segment_sums(b, G, gseg_sum, gseg_lane);
 }
 
 // What the chunk records need of a stream.
@@ -391,15 +420,18 @@ __device__ inline int64_t wave_sum64(int64_t v) {
 __global__ void __launch_bounds__(kSumThreads) k_plan_seg_chunks(fptc_batch b, int N, int E, int wpc,
                                                                   const int64_t *hdr, const int64_t *win_off,
                                                                   const int64_t *chunk_off, const int64_t *seg_off,
-                                                                  const int32_t *seg_stream, const int32_t *seg_sum,
-                                                                  ChunkMeta *meta, int32_t *status) {
+                                                                  const int32_t *seg_stream, const int32_t *gseg_sum,
+                                                                  const int32_t *gseg_lane, ChunkMeta *meta,
+                                                                  int32_t *status) {
   constexpr int WPT = kSegWords / kSumThreads;
   __shared__ uint32_t counts[kSegWords / 4];  // lane l's packed counts at [l * WPT / 4, (l + 1) * WPT / 4)
   __shared__ int lane_at[kWave + 1];          // exclusive prefix of the lanes' totals, then the total
   if (b.n_streams <= 0) return;
   const int64_t g = blockIdx.x;
   const int lane = threadIdx.x;
-  // as in k_plan_seg_sums: the stream index is clamped before any read with it
+  // g < seg_cap, so this read is in bounds; past the plan's pieces it may
+  // hold anything, so it is clamped to a stream before the stream's offsets
+  // are read with it (such a wavefront then returns on the check below)
   const int s = clamp_stream(seg_stream[g], b.n_streams);
   const int64_t h2 = hdr[2], seg_cap = hdr[3];
   // everything of the stream at once: one round trip before the words
@@ -416,20 +448,31 @@ __global__ void __launch_bounds__(kSumThreads) k_plan_seg_chunks(fptc_batch b, i
   r.book = b.book_id ? (int)b.book_id[s] : 0;
   pin(t.w0), pin(t.w1), pin(t.g0), pin(t.g1), pin(h2), pin(seg_cap), pin(r.c0), pin(r.nc), pin(r.wo0), pin(r.nw),
       pin(r.so), pin(r.L);
-  if (g >= h2 || t.g1 > seg_cap || r.nc <= 0) return;  // past the plan, or a stream without chunks
-  // the earlier segments' sums: at most a few per lane, loaded beside the words
+  // past the plan, a stream without chunks, or (never, with the stream
+  // pass's map) a piece outside its stream's pieces
+  if (g >= h2 || t.g1 > seg_cap || r.nc <= 0 || g < t.g0 || g >= t.g1) return;
+  // The stream's symbols before this piece: the whole segments from the
+  // stream's first one up to this one, less what of the first precedes the
+  // stream's first word w0 (its 64-word blocks before w0's, then w0's block
+  // up to w0).  All of these words exist (w0 <= the piece's first word).
   int64_t before = 0;
-  {
-    const int64_t i0 = t.g0 + lane;
-    int32_t v0 = 0, v1 = 0, v2 = 0;
-    if (i0 < g) v0 = seg_sum[i0];
-    if (i0 + kWave < g) v1 = seg_sum[i0 + kWave];
-    if (i0 + 2 * kWave < g) v2 = seg_sum[i0 + 2 * kWave];
-    before = (int64_t)v0 + v1 + v2;
-    for (int64_t i = i0 + 3 * kWave; i < g; i += kWave) before += seg_sum[i];  // streams of > 192 segments
+  const int64_t j = g - t.g0;  // this piece's index in the stream
+  if (j > 0) {
+    const int64_t G0 = t.w0 >> kSegShift;
+    const int l0 = (int)((t.w0 - (G0 << kSegShift)) >> 6);
+    const int64_t blk = (G0 << kSegShift) + ((int64_t)l0 << 6);
+    int64_t v = 0;
+    const int32_t a0 = lane < j ? gseg_sum[G0 + lane] : 0;
+    const int32_t a1 = lane + kWave < j ? gseg_sum[G0 + lane + kWave] : 0;
+    const int pre = blk + lane < t.w0 ? (int)b.symlen[blk + lane] : 0;
+    const int32_t pl = lane == 0 ? gseg_lane[(G0 << 6) + l0] : 0;
+    v = (int64_t)a0 + a1 - (pre > 64 ? 64 : pre) - pl;
+    for (int64_t i = lane + 2 * kWave; i < j; i += kWave) v += gseg_sum[G0 + i];  // streams of > 128 segments
+    before = v;
   }
   SegWords<WPT> sw;
-  load_seg_words(b, g, t, sw);
+  const int bad = load_seg_words(b, g, t, sw);
+  if (bad && status) atomicOr(&status[s], bad);
 #pragma unroll
   for (int q = 0; q < WPT / 16; ++q)
     *reinterpret_cast<uint4 *>(&counts[lane * (WPT / 4) + 4 * q]) =
@@ -438,7 +481,7 @@ __global__ void __launch_bounds__(kSumThreads) k_plan_seg_chunks(fptc_batch b, i
   const int ex = seg_excl_scan(seg_words_sum(sw), tot);
   lane_at[lane] = ex;
   if (lane == 0) lane_at[kWave] = tot;
-  before = wave_sum64(before);
+  if (j > 0) before = wave_sum64(before);
   wave_sync_lds();
   const int64_t cb = (int64_t)wpc * E;  // symbols per chunk
   const int64_t m_lo = (before + cb - 1) / cb;
@@ -484,16 +527,15 @@ __global__ void __launch_bounds__(kSumThreads) k_plan_seg_chunks(fptc_batch b, i
 int launch_plan(const fptc_batch &b, const fptc_codec &c, const Shape &s, const Plan &p, int32_t *status,
                 void *stream) {
   hipStream_t st = (hipStream_t)stream;
-  hipLaunchKernelGGL(k_plan_streams, dim3(1), dim3(kPlanThreads), 0, st, b, c.N, c.E, s.wpc, p.hdr, p.win_off,
-                     p.chunk_off, p.seg_off, p.seg_stream, p.seg_cap, status);
+  const int64_t sum_blocks = (p.n_gseg + kSumWavesPerBlock - 1) / kSumWavesPerBlock;
+  hipLaunchKernelGGL(k_plan_pass1, dim3((unsigned)(1 + sum_blocks)), dim3(kPlanThreads), 0, st, b, c.N, c.E, s.wpc,
+                     p.hdr, p.win_off, p.chunk_off, p.seg_off, p.seg_stream, p.seg_cap, p.gseg_sum, p.gseg_lane,
+                     p.n_gseg, status);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return (int)e;
-  const unsigned nseg = (unsigned)(p.seg_cap > 0 ? p.seg_cap : 1);  // blocks past hdr[2] exit at once
-  hipLaunchKernelGGL(k_plan_seg_sums, dim3(nseg), dim3(kSumThreads), 0, st, b, p.hdr, p.chunk_off, p.seg_off,
-                     p.seg_stream, p.seg_sum, status);
-  if ((e = hipGetLastError()) != hipSuccess) return (int)e;
+  const unsigned nseg = (unsigned)(p.seg_cap > 0 ? p.seg_cap : 1);  // wavefronts past hdr[2] exit at once
   hipLaunchKernelGGL(k_plan_seg_chunks, dim3(nseg), dim3(kSumThreads), 0, st, b, c.N, c.E, s.wpc, p.hdr, p.win_off,
-                     p.chunk_off, p.seg_off, p.seg_stream, p.seg_sum, p.chunk_meta, status);
+                     p.chunk_off, p.seg_off, p.seg_stream, p.gseg_sum, p.gseg_lane, p.chunk_meta, status);
   return (int)hipGetLastError();
 }
 
