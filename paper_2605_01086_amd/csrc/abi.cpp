@@ -67,8 +67,8 @@ Layout layout_for(const fptc_batch *b, const fptc_codec *c, const Shape &s) {
   // touch: with disjoint word ranges at most n_words / 4096 + 2 n in all
   L.seg_cap = b->n_words / 4096 + 2 * n + 1;
   L.n_gseg = (b->n_words + 4095) / 4096;
-  L.seg_stream = off;
-  off = align256(off + L.seg_cap * sizeof(int32_t));
+  L.seg_map = off;
+  off = align256(off + L.seg_cap * 2 * sizeof(int32_t));
   L.gseg_sum = off;
   off = align256(off + L.n_gseg * sizeof(int32_t));
   L.gseg_lane = off;
@@ -90,7 +90,7 @@ Plan plan_view(void *ws, const Layout &L) {
   v.bwd_part = reinterpret_cast<double *>(p + L.bwd_part);
   v.chunk_meta = reinterpret_cast<ChunkMeta *>(p + L.chunk_meta);
   v.seg_off = reinterpret_cast<int64_t *>(p + L.seg_off);
-  v.seg_stream = reinterpret_cast<int32_t *>(p + L.seg_stream);
+  v.seg_map = reinterpret_cast<int32_t *>(p + L.seg_map);
   v.gseg_sum = reinterpret_cast<int32_t *>(p + L.gseg_sum);
   v.gseg_lane = reinterpret_cast<int32_t *>(p + L.gseg_lane);
   v.chunk_cap = L.chunk_cap;

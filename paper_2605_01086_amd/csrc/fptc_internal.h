@@ -54,13 +54,13 @@ struct Shape {
 //   chunk_off  int64[n+1]   exclusive prefix of ceil(n_win_s / wpc) (0 for streams
 //                           flagged by the stream pass)
 //   seg_off    int64[n+1]   exclusive prefix of each stream's segment pieces
-//   seg_stream int32[scap]  stream of each piece
+//   seg_map    int32[scap*2] stream and segment of each piece
 //   gseg_sum   int32[nseg]  symbols of each 4096-word segment of the batch
 //   gseg_lane  int32[nseg*64] exclusive prefix of its 64-word blocks
 //   bwd_part   double[cap*3] backward partial sums per chunk and zone
 //   chunk_meta ChunkMeta[cap] per-chunk decode record
 struct Layout {
-  size_t hdr, win_off, chunk_off, seg_off, bwd_part, seg_stream, gseg_sum, gseg_lane, chunk_meta, total;
+  size_t hdr, win_off, chunk_off, seg_off, bwd_part, seg_map, gseg_sum, gseg_lane, chunk_meta, total;
   int64_t chunk_cap, seg_cap, n_gseg;
 };
 
@@ -73,7 +73,7 @@ struct Plan {
   int64_t *chunk_off;
   double *bwd_part;
   int64_t *seg_off;     // [n_streams + 1] symlen segments per stream, prefix
-  int32_t *seg_stream;  // [seg_cap] stream of each piece (a stream's words in one segment)
+  int32_t *seg_map;     // [seg_cap * 2] stream and segment of each piece (a stream's words in one segment)
   int32_t *gseg_sum;    // [n_gseg] symbols of each segment of the batch
   int32_t *gseg_lane;   // [n_gseg * 64] exclusive prefix of each segment's 64-word blocks
   ChunkMeta *chunk_meta;

@@ -103,11 +103,12 @@ __device__ inline int64_t ceil_div(int64_t a, int d) {
 constexpr int kStreamsPerThread = 4;
 
 __device__ void stream_pass(const fptc_batch &b, int N, int E, int wpc, int64_t *hdr, int64_t *win_off,
-                            int64_t *chunk_off, int64_t *seg_off, int32_t *seg_stream, int64_t seg_cap,
+                            int64_t *chunk_off, int64_t *seg_off, int2 *seg_map, int64_t seg_cap,
                             int32_t *status) {
   __shared__ int64_t lds[2 * (kPlanThreads / kWave + 1)];
   constexpr int K = kStreamsPerThread;
-  __shared__ int64_t seg_at[kPlanThreads * K + 1];  // this pass's streams: first segment of each, then the end
+  __shared__ int64_t seg_at[kPlanThreads * K + 1];  // this pass's streams: first piece of each, then the end
+  __shared__ int32_t seg_g0[kPlanThreads * K];      // this pass's streams: the segment of each one's first word
   const int n = b.n_streams;
   const int64_t win_cap = b.n_symbols / E;
   int64_t carry_w = 0, carry_c = 0, carry_g = 0;
@@ -174,25 +175,41 @@ __device__ void stream_pass(const fptc_batch &b, int N, int E, int wpc, int64_t 
         if (status) status[s] = flag[k];
       }
       seg_at[threadIdx.x * K + k] = gx[k];  // past n: the pass's end
+      seg_g0[threadIdx.x * K + k] = (int32_t)(wo[k] >> kSegShift);
       c_at += nc[k];
     }
     if (threadIdx.x == 0) seg_at[kPlanThreads * K] = carry_g;
     __syncthreads();
-    // segment -> stream map: each thread a contiguous range of this pass's
-    // segments, its first stream by binary search, then walking forward
-    const int64_t per = (g_tot + kPlanThreads - 1) / kPlanThreads;
-    const int64_t g_lo = g_pass + (int64_t)threadIdx.x * per, g_hi = min(g_lo + per, carry_g);
+    // piece -> (stream, segment) map: each thread a contiguous range of this
+    // pass's pieces (an even number, so that aligned pairs leave as one
+    // 16-byte store), its first stream by binary search, then walking forward
+    const int64_t per = ((g_tot + kPlanThreads - 1) / kPlanThreads + 1) & ~(int64_t)1;
+    const int64_t g_lo = g_pass + (int64_t)threadIdx.x * per;
+    const int64_t g_hi = min(min(g_lo + per, carry_g), seg_cap);
     if (g_lo < g_hi) {
-      int lo = 0, hi = kPlanThreads * K - 1;  // last local stream whose first segment is <= g_lo
+      int lo = 0, hi = kPlanThreads * K - 1;  // last local stream whose first piece is <= g_lo
       while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
         if (seg_at[mid] <= g_lo) lo = mid;
         else hi = mid - 1;
       }
       int i = lo;
-      for (int64_t g = g_lo; g < g_hi && g < seg_cap; ++g) {
-        while (seg_at[i + 1] <= g) ++i;
-        seg_stream[g] = base + i;
+      for (int64_t g = g_lo; g < g_hi; g += 2) {
+        int2 v[2];
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          // g + q < g_hi <= the pass's end = seg_at[kPlanThreads * K]: the walk stops inside
+          if (g + q < g_hi)
+            while (seg_at[i + 1] <= g + q) ++i;
+          v[q] = make_int2(base + i, seg_g0[i] + (int32_t)(g + q - seg_at[i]));
+        }
+        if (g + 2 <= g_hi && ((reinterpret_cast<uintptr_t>(seg_map + g) & 15) == 0)) {
+          *reinterpret_cast<int4 *>(seg_map + g) = make_int4(v[0].x, v[0].y, v[1].x, v[1].y);
+        } else {
+#pragma unroll
+          for (int q = 0; q < 2; ++q)
+            if (g + q < g_hi) seg_map[g + q] = v[q];
+        }
       }
     }
     __syncthreads();
@@ -240,61 +257,66 @@ __device__ inline SegStream seg_stream_of(const fptc_batch &b, int s, const int6
   return t;
 }
 
-template <int WPT>
-__device__ inline int load_seg_words(const fptc_batch &b, int64_t g, const SegStream &t, SegWords<WPT> &sw) {
-  static_assert(WPT % 16 == 0, "whole 16-byte symlen blocks per thread");
-  const int64_t a0 = t.w0 & ~(kSegWords - 1);  // the stream's first segment
-  const int64_t first = a0 + (g - t.g0) * kSegWords + (int64_t)(threadIdx.x & (kWave - 1)) * WPT;
-  sw.first = first;
-  const bool aligned = (reinterpret_cast<uintptr_t>(b.symlen) & 15) == 0;
+// Each byte of four packed symlen counts clamped to 64.
+__device__ inline uint32_t clamp64x4(uint32_t v) {
+  if (!((v & 0x80808080u) | (((v & 0x7f7f7f7fu) + 0x3f3f3f3fu) & 0x80808080u))) return v;
+  uint32_t c = 0;
 #pragma unroll
-  for (int q = 0; q < WPT / 16; ++q) {
-    const int64_t f = first + 16 * q;
-    uint32_t *x = sw.x + 4 * q;
-    x[0] = x[1] = x[2] = x[3] = 0;
-    if (f + 16 <= t.w0 || f >= t.w1) continue;  // no word of the stream
-    if (aligned && f + 16 <= b.n_words) {
-      // a whole 16-byte block inside the array (f is a multiple of 16);
-      // bytes outside the stream are cleared below
-      const uint4 u = *reinterpret_cast<const uint4 *>(b.symlen + f);
-      x[0] = u.x, x[1] = u.y, x[2] = u.z, x[3] = u.w;
-    } else {
-#pragma unroll
-      for (int j = 0; j < 16; ++j)
-        if (f + j >= t.w0 && f + j < t.w1) x[j >> 2] |= (uint32_t)b.symlen[f + j] << (8 * (j & 3));
-    }
+  for (int k = 0; k < 4; ++k) {
+    const uint32_t e = (v >> (8 * k)) & 255u;
+    c |= (e > 64u ? 64u : e) << (8 * k);
   }
-  // clear the bytes before the stream's first and from its last word on
-  // (only the lanes at the stream's two ends have any)
-  const int64_t lo64 = t.w0 - first, hi64 = t.w1 - first;
-  if (lo64 > 0 || hi64 < WPT) {
+  return c;
+}
+
+// Segment G's symlen bytes for this lane: words [kSegWords G + WPT lane,
+// + WPT), packed four to a dword; words past the array read as 0.  0 <= G.
+template <int WPT>
+__device__ inline void load_segment_words(const fptc_batch &b, int64_t G, SegWords<WPT> &sw) {
+  static_assert(WPT % 16 == 0, "whole 16-byte symlen blocks per thread");
+  const int64_t first = (G << kSegShift) + (int64_t)(threadIdx.x & (kWave - 1)) * WPT;
+  sw.first = first;
+  if ((reinterpret_cast<uintptr_t>(b.symlen) & 15) == 0 && first + WPT <= b.n_words) {
+    // the lane's whole range inside the array: its 16-byte loads back to back
+    // (first is a multiple of 16)
+    const uint4 *src = reinterpret_cast<const uint4 *>(b.symlen + first);
+#pragma unroll
+    for (int q = 0; q < WPT / 16; ++q) {
+      const uint4 u = src[q];
+      sw.x[4 * q] = u.x, sw.x[4 * q + 1] = u.y, sw.x[4 * q + 2] = u.z, sw.x[4 * q + 3] = u.w;
+    }
+  } else {
+#pragma unroll
+    for (int d = 0; d < WPT / 4; ++d) sw.x[d] = 0;
+    for (int j = 0; j < WPT && first + j < b.n_words; ++j) sw.x[j >> 2] |= (uint32_t)b.symlen[first + j] << (8 * (j & 3));
+  }
+}
+
+// Keep the stream's words [w0, w1) of a loaded segment (the others read as
+// 0); a count above 64 is clamped to 64 and reported.
+template <int WPT>
+__device__ inline int keep_stream_words(SegWords<WPT> &sw, const SegStream &t) {
+  const int64_t lo64 = t.w0 - sw.first, hi64 = t.w1 - sw.first;
+  if (lo64 > 0 || hi64 < WPT) {  // only the lanes at the stream's two ends, or outside it
     const int lo = lo64 > 0 ? (int)(lo64 < WPT ? lo64 : WPT) : 0;
     const int hi = hi64 < WPT ? (int)(hi64 > 0 ? hi64 : 0) : WPT;
 #pragma unroll
     for (int d = 0; d < WPT / 4; ++d) {
-      uint32_t m = 0;
-#pragma unroll
-      for (int k = 0; k < 4; ++k) m |= (4 * d + k >= lo && 4 * d + k < hi) ? (255u << (8 * k)) : 0u;
-      sw.x[d] &= m;
+      // bytes [lo - 4 d, hi - 4 d) of this dword, each bound clamped to [0, 4]
+      const int a = min(max(lo - 4 * d, 0), 4), e = min(max(hi - 4 * d, 0), 4);
+      const uint32_t keep_hi = (uint32_t)(((uint64_t)1 << (8 * e)) - 1);  // bytes below e
+      const uint32_t drop_lo = (uint32_t)(((uint64_t)1 << (8 * a)) - 1);  // bytes below a
+      sw.x[d] &= keep_hi & ~drop_lo;
     }
   }
-  // a count above 64 (a byte of 65 or more) is clamped and reported
   int bad = 0;
 #pragma unroll
   for (int d = 0; d < WPT / 4; ++d) {
-    const uint32_t v = sw.x[d];
-    if ((v & 0x80808080u) | (((v & 0x7f7f7f7fu) + 0x3f3f3f3fu) & 0x80808080u)) {
-      uint32_t c = 0;
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        const uint32_t e = (v >> (8 * k)) & 255u;
-        c |= (e > 64u ? 64u : e) << (8 * k);
-      }
-      sw.x[d] = c;
-      bad = FPTC_STREAM_BAD_SYMLEN;
-    }
+    const uint32_t c = clamp64x4(sw.x[d]);
+    bad |= c != sw.x[d];
+    sw.x[d] = c;
   }
-  return bad;
+  return bad ? FPTC_STREAM_BAD_SYMLEN : 0;
 }
 
 // The sum of a thread's counts.
@@ -313,41 +335,16 @@ __device__ inline int seg_excl_scan(int v, int &total) {
   return incl - v;
 }
 
-// Each byte of four packed symlen counts clamped to 64.
-__device__ inline uint32_t clamp64x4(uint32_t v) {
-  if (!((v & 0x80808080u) | (((v & 0x7f7f7f7fu) + 0x3f3f3f3fu) & 0x80808080u))) return v;
-  uint32_t c = 0;
-#pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    const uint32_t e = (v >> (8 * k)) & 255u;
-    c |= (e > 64u ? 64u : e) << (8 * k);
-  }
-  return c;
-}
-
 // One wavefront: segment G's symbol count and the exclusive prefix of its
 // 64-word blocks (symlen clamped to 64, as everywhere in the plan; the flag
 // for a larger one is raised where a stream's words are read).
 __device__ void segment_sums(const fptc_batch &b, int64_t G, int32_t *gseg_sum, int32_t *gseg_lane) {
   const int lane = threadIdx.x & (kWave - 1);
-  const int64_t f0 = (G << kSegShift) + (int64_t)lane * 64;
-  const bool aligned = (reinterpret_cast<uintptr_t>(b.symlen) & 15) == 0;
+  SegWords<kSegWords / kWave> sw;
+  load_segment_words(b, G, sw);
   uint32_t sum = 0;
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int64_t f = f0 + 16 * q;
-    uint32_t x[4] = {0u, 0u, 0u, 0u};
-    if (aligned && f + 16 <= b.n_words) {
-      const uint4 u = *reinterpret_cast<const uint4 *>(b.symlen + f);
-      x[0] = u.x, x[1] = u.y, x[2] = u.z, x[3] = u.w;
-    } else {
-#pragma unroll
-      for (int j = 0; j < 16; ++j)
-        if (f + j < b.n_words) x[j >> 2] |= (uint32_t)b.symlen[f + j] << (8 * (j & 3));
-    }
-#pragma unroll
-    for (int d = 0; d < 4; ++d) sum = __builtin_amdgcn_sad_u8(clamp64x4(x[d]), 0u, sum);
-  }
+  for (int d = 0; d < kSegWords / kWave / 4; ++d) sum = __builtin_amdgcn_sad_u8(clamp64x4(sw.x[d]), 0u, sum);
   const int incl = wave_incl_scan_dpp((int)sum);
   gseg_lane[(G << 6) + lane] = incl - (int)sum;
   if (lane == kWave - 1) gseg_sum[G] = incl;
@@ -359,10 +356,10 @@ constexpr int kSumWavesPerBlock = kPlanThreads / kWave;
 
 __global__ void __launch_bounds__(kPlanThreads) k_plan_pass1(fptc_batch b, int N, int E, int wpc, int64_t *hdr,
                                                              int64_t *win_off, int64_t *chunk_off, int64_t *seg_off,
-                                                             int32_t *seg_stream, int64_t seg_cap, int32_t *gseg_sum,
+                                                             int2 *seg_map, int64_t seg_cap, int32_t *gseg_sum,
                                                              int32_t *gseg_lane, int64_t n_gseg, int32_t *status) {
   if (blockIdx.x == 0) {
-    stream_pass(b, N, E, wpc, hdr, win_off, chunk_off, seg_off, seg_stream, seg_cap, status);
+    stream_pass(b, N, E, wpc, hdr, win_off, chunk_off, seg_off, seg_map, seg_cap, status);
     return;
   }
   const int64_t G = (int64_t)(blockIdx.x - 1) * kSumWavesPerBlock + (threadIdx.x >> 6);
@@ -420,21 +417,24 @@ __device__ inline int64_t wave_sum64(int64_t v) {
 __global__ void __launch_bounds__(kSumThreads) k_plan_seg_chunks(fptc_batch b, int N, int E, int wpc,
                                                                   const int64_t *hdr, const int64_t *win_off,
                                                                   const int64_t *chunk_off, const int64_t *seg_off,
-                                                                  const int32_t *seg_stream, const int32_t *gseg_sum,
-                                                                  const int32_t *gseg_lane, ChunkMeta *meta,
-                                                                  int32_t *status) {
+                                                                  const int2 *seg_map, int64_t n_gseg,
+                                                                  const int32_t *gseg_sum, const int32_t *gseg_lane,
+                                                                  ChunkMeta *meta, int32_t *status) {
   constexpr int WPT = kSegWords / kSumThreads;
   __shared__ uint32_t counts[kSegWords / 4];  // lane l's packed counts at [l * WPT / 4, (l + 1) * WPT / 4)
   __shared__ int lane_at[kWave + 1];          // exclusive prefix of the lanes' totals, then the total
-  if (b.n_streams <= 0) return;
+  if (b.n_streams <= 0 || n_gseg <= 0) return;
   const int64_t g = blockIdx.x;
   const int lane = threadIdx.x;
   // g < seg_cap, so this read is in bounds; past the plan's pieces it may
-  // hold anything, so it is clamped to a stream before the stream's offsets
-  // are read with it (such a wavefront then returns on the check below)
-  const int s = clamp_stream(seg_stream[g], b.n_streams);
+  // hold anything, so the stream and the segment are clamped before any read
+  // with them (such a wavefront then returns on the check below)
+  const int2 sg = seg_map[g];
+  const int s = clamp_stream(sg.x, b.n_streams);
+  const int64_t G = sg.y < 0 ? 0 : (sg.y >= n_gseg ? n_gseg - 1 : (int64_t)sg.y);
+  // everything of the stream at once, then the segment's words beside it:
+  // one round trip
   const int64_t h2 = hdr[2], seg_cap = hdr[3];
-  // everything of the stream at once: one round trip before the words
   const SegStream t = seg_stream_of(b, s, seg_off);
   StreamChunks r;
   r.c0 = chunk_off[s];
@@ -446,6 +446,8 @@ __global__ void __launch_bounds__(kSumThreads) k_plan_seg_chunks(fptc_batch b, i
   r.w1 = t.w1;
   r.s = s;
   r.book = b.book_id ? (int)b.book_id[s] : 0;
+  SegWords<WPT> sw;
+  load_segment_words(b, G, sw);
   pin(t.w0), pin(t.w1), pin(t.g0), pin(t.g1), pin(h2), pin(seg_cap), pin(r.c0), pin(r.nc), pin(r.wo0), pin(r.nw),
       pin(r.so), pin(r.L);
   // past the plan, a stream without chunks, or (never, with the stream
@@ -470,8 +472,7 @@ __global__ void __launch_bounds__(kSumThreads) k_plan_seg_chunks(fptc_batch b, i
     for (int64_t i = lane + 2 * kWave; i < j; i += kWave) v += gseg_sum[G0 + i];  // streams of > 128 segments
     before = v;
   }
-  SegWords<WPT> sw;
-  const int bad = load_seg_words(b, g, t, sw);
+  const int bad = keep_stream_words(sw, t);
   if (bad && status) atomicOr(&status[s], bad);
 #pragma unroll
   for (int q = 0; q < WPT / 16; ++q)
@@ -529,13 +530,15 @@ int launch_plan(const fptc_batch &b, const fptc_codec &c, const Shape &s, const 
   hipStream_t st = (hipStream_t)stream;
   const int64_t sum_blocks = (p.n_gseg + kSumWavesPerBlock - 1) / kSumWavesPerBlock;
   hipLaunchKernelGGL(k_plan_pass1, dim3((unsigned)(1 + sum_blocks)), dim3(kPlanThreads), 0, st, b, c.N, c.E, s.wpc,
-                     p.hdr, p.win_off, p.chunk_off, p.seg_off, p.seg_stream, p.seg_cap, p.gseg_sum, p.gseg_lane,
+                     p.hdr, p.win_off, p.chunk_off, p.seg_off, reinterpret_cast<int2 *>(p.seg_map), p.seg_cap,
+                     p.gseg_sum, p.gseg_lane,
                      p.n_gseg, status);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return (int)e;
   const unsigned nseg = (unsigned)(p.seg_cap > 0 ? p.seg_cap : 1);  // wavefronts past hdr[2] exit at once
   hipLaunchKernelGGL(k_plan_seg_chunks, dim3(nseg), dim3(kSumThreads), 0, st, b, c.N, c.E, s.wpc, p.hdr, p.win_off,
-                     p.chunk_off, p.seg_off, p.seg_stream, p.gseg_sum, p.gseg_lane, p.chunk_meta, status);
+                     p.chunk_off, p.seg_off, reinterpret_cast<const int2 *>(p.seg_map), p.n_gseg, p.gseg_sum,
+                     p.gseg_lane, p.chunk_meta, status);
   return (int)hipGetLastError();
 }
 
