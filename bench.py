@@ -161,9 +161,11 @@ class Setup:
 
 
 def kernel_name(stage: str, N: int, precision: str) -> str:
-    w = "256" if N == 256 else ""
-    return {"plan": PLAN_KERNELS, "fused": f"k_fused{w}<{precision}>", "decode": "k_decode",
-            "dequant_idct": "k_dqidct_f32" if precision == "fp32" else f"k_dqidct_mfma{w}<{precision}>",
+    wide = N == 256
+    return {"plan": PLAN_KERNELS, "fused": f"k_w256<{precision}, fused>" if wide else f"k_fused<{precision}>",
+            "decode": "k_decode",
+            "dequant_idct": "k_dqidct_f32" if precision == "fp32" else
+            (f"k_w256<{precision}, split>" if wide else f"k_dqidct_mfma<{precision}>"),
             "backward": ("k_bwd_mfma" if N in (32, 64, 128) else "k_bwd_chunk") + "+k_bwd_streams"}[stage]
 
 

@@ -114,3 +114,52 @@ def test_zone2_is_always_zero(O):
         assert all(O.dequant_paper(s, k, p) == 0.0 for s in range(256))
         assert all(O.zone(s, k, p) == 2 for s in range(256))
     assert O.zone(17, 0, p) == 0 and O.zone(17, 1, p) == 0 and O.zone(17, 2, p) == 1 and O.zone(17, 7, p) == 1
+
+
+# Stream-level encode side (Section 3.1 transform, Section 3.2 quantizer,
+# Section 3.3 histogram): each is the composition of pinned pieces, checked
+# here against that composition written out, plus numpy's own routines.
+
+@pytest.mark.parametrize("kind,N,E", [("amp", 16, 16), ("amp", 64, 20), ("paper", 32, 16)])
+def test_quantize_stream_is_the_per_coefficient_quantizer_of_the_window_transform(O, kind, N, E):
+    rng = np.random.default_rng(70 + N + E)
+    x = (rng.standard_normal(3 * N + 5) * 4.0).astype(np.float32)
+    if kind == "amp":
+        p = O.QuantParams("amp", N, E, **AMP)
+    else:
+        p = O.QuantParams("paper", N, E, B1=2, B2=E, mu=50.0, alpha1=0.004, A0=9.0, A1=5.0)
+    coef = O.dct_stream(x, N, E).reshape(-1, E)
+    want = np.empty(coef.shape, dtype=np.uint8)
+    for w in range(coef.shape[0]):
+        for k in range(E):
+            c = float(coef[w, k])
+            want[w, k] = O.quant_amp(c, p.step_f, p.step_c, p.T) if kind == "amp" else O.quant_paper(c, k, p)
+    assert np.array_equal(O.quantize_stream(x, p), want.ravel())
+
+
+def test_histogram_equals_bincount(O):
+    rng = np.random.default_rng(71)
+    for n in (0, 1, 257, 10000):
+        sym = rng.integers(0, 256, size=n, dtype=np.uint8)
+        sym[: n // 3] = 128  # a dominant symbol, as the quantizers give
+        assert np.array_equal(O.histogram(sym), np.bincount(sym, minlength=256).astype(np.uint64))
+
+
+def test_zone_maxima_are_order_statistics_of_the_zones(O):
+    # the linear percentile at 0 / 100 is the zone's min / max of |c|, and
+    # between two order statistics it interpolates (checked on a tiny case
+    # by sorting by hand)
+    N, E, B1, B2 = 16, 8, 2, 6
+    rng = np.random.default_rng(72)
+    x = (rng.standard_normal(5 * N) * 3.0).astype(np.float32)
+    p = O.QuantParams("paper", N, E, B1=B1, B2=B2, mu=50.0, alpha1=0.004, A0=1.0, A1=1.0)
+    coef = np.abs(O.dct_stream(x, N, E).reshape(-1, E))
+    z0, z1 = np.sort(coef[:, :B1].ravel()), np.sort(coef[:, B1:B2].ravel())
+    assert O.paper_zone_maxima(x, p, 100.0) == (z0[-1], z1[-1])
+    assert O.paper_zone_maxima(x, p, 0.0) == (z0[0], z1[0])
+    q = 99.9
+    for z, got in zip((z0, z1), O.paper_zone_maxima(x, p, q)):
+        pos = q / 100.0 * (z.size - 1)
+        i = int(np.floor(pos))
+        want = z[i] + (pos - i) * (z[min(i + 1, z.size - 1)] - z[i])
+        assert abs(got - want) <= 1e-12 * max(1.0, abs(want))
