@@ -47,7 +47,7 @@ extern "C" {
 typedef enum {
   FPTC_OK = 0,
   FPTC_ERR_INVALID_ARG = 1, /* NULL pointer, size out of range, inconsistent sizes */
-  FPTC_ERR_UNSUPPORTED = 2, /* valid request this build does not implement */
+  FPTC_ERR_UNSUPPORTED = 2, /* valid request the library does not implement */
   FPTC_ERR_WORKSPACE = 3,   /* workspace smaller than fptc_workspace_size() */
   FPTC_ERR_HIP = 4          /* a HIP runtime call or kernel launch failed */
 } fptc_status;
