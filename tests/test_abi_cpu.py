@@ -240,3 +240,18 @@ def test_dct_table_rejects_bad_sizes():
         F.fptc_build_dct_table(12, 4)
     with pytest.raises(F.FptcError):
         F.fptc_build_dct_table(64, 65)
+
+
+def test_window_sample_index_matches_a_loop():
+    # the output position of every window sample (the coefficient input of
+    # the autograd Function scatters through it)
+    from paper_2605_01086_amd.refit import window_sample_index
+    for N, lens in [(4, [0, 1, 4, 5, 9]), (64, [64 * 3 + 7, 0, 1, 128]), (256, [300, 256, 2])]:
+        so = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+        want = []
+        for s, L in enumerate(lens):
+            for w in range((L + N - 1) // N):
+                for n in range(N):
+                    pos = w * N + n
+                    want.append(so[s] + pos if pos < L else -1)
+        assert np.array_equal(window_sample_index(so, N), np.array(want, dtype=np.int64))

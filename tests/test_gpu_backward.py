@@ -125,6 +125,51 @@ def test_autograd_and_adam_refit(precision):
     np.testing.assert_allclose(gamma.cpu().numpy(), og, atol=2e-3)
 
 
+@pytest.mark.parametrize("N,E", [(128, 128), (32, 16)])
+def test_autograd_coefficient_input(N, E):
+    """The autograd Function's additive coefficient input: its gradient is the
+    oracle's coefficient gradient of the MSE, and its forward term is the
+    oracle's per-window inverse DCT of the coefficients."""
+    import torch
+    from oracle import oracle as O
+    from paper_2605_01086_amd import refit as R
+    p = _amp(N, E)
+    c = build_case(p, ["power", "eeg"], [N * 33 + 5, N * 12, 7], config_id=2350 + N, recon=False)
+    dec = _decoder(c)
+    x = torch.from_numpy(np.concatenate(c.signals)).cuda()
+    n_sym = dec.batch.n_symbols
+    g = torch.ones((len(c.signals), 3), dtype=torch.float64, device="cuda")
+    delta = torch.zeros(n_sym, dtype=torch.float32, device="cuda", requires_grad=True)
+    loss = R.mse(R.DequantIDCT.apply(g, dec, "fp32", delta), x)
+    loss.backward()
+    got = delta.grad.cpu().numpy()
+    M = x.numel()
+    for i, xi in enumerate(c.signals):
+        xh = O.reconstruct(c.symbols[i], len(xi), p, None)
+        ogc, _ = O.backward(c.symbols[i], len(xi), p, 2.0 * (xh - xi.astype(np.float64)) / M)
+        s0, s1 = dec.batch.sym_off_h[i], dec.batch.sym_off_h[i + 1]
+        scale = max(1e-30, np.abs(ogc).max())
+        assert np.max(np.abs(got[s0:s1] - ogc)) <= 1e-5 * scale, i
+    # forward: out(delta) - out(0) = the inverse DCT of delta, window by window
+    rng = np.random.default_rng(N + E)
+    dv = rng.standard_normal(n_sym).astype(np.float32)
+    with torch.no_grad():
+        dvt = torch.from_numpy(dv).cuda()
+        a = R.DequantIDCT.apply(g, dec, "fp32", dvt).cpu().numpy()
+        b = R.DequantIDCT.apply(g, dec, "fp32").cpu().numpy()
+        term = R.idct_coefficients(dec, dvt).cpu().numpy()
+    # the forward adds the term (one float32 rounding of the sum)
+    assert np.all(np.abs(a - (b + term)) <= 2 * np.finfo(np.float32).eps * np.maximum(np.abs(a), 1.0))
+    so = dec.batch.sample_off_h
+    for i, xi in enumerate(c.signals):
+        s0 = dec.batch.sym_off_h[i]
+        nw = O.n_windows(len(xi), N)
+        want = np.concatenate([O.idct_ortho(dv[s0 + w * E:s0 + (w + 1) * E].astype(np.float64), N, E)
+                               for w in range(nw)])[:len(xi)] if nw else np.zeros(0)
+        got_i = term[so[i]:so[i + 1]]
+        assert np.max(np.abs(got_i - want), initial=0.0) <= 1e-5 * max(1.0, np.abs(want).max(initial=0.0)), i
+
+
 def test_differentiation_workload_full_size_sampled():
     """256 power/met streams of 2^18 samples at W = 128: full-size forward +
     backward on the GPU, scale gradients of sampled streams against the oracle."""
