@@ -220,7 +220,7 @@ def time_graph(dec, precision, fused, steps, warmup):
     return ms
 
 
-def read_summary(name: str, stage: str):
+def read_summary(name: str, stage: str, wide: bool = False):
     """key: value lines of profiles/<name>.txt, or None when absent or taken on
     other kernel sources than the ones built now."""
     path = os.path.join(ROOT, "profiles", f"{name}.txt")
@@ -232,26 +232,30 @@ def read_summary(name: str, stage: str):
             if ":" in line and not line.startswith("#"):
                 k, v = line.split(":", 1)
                 kv[k.strip()] = v.strip()
-    if kv.get("source_sha256") != source_digest(stage):
+    if kv.get("source_sha256") != source_digest(stage, wide):
         return None, "kernel changed since the counters were taken"
     return kv, path[len(ROOT) + 1:]
 
 
-# Sources of each stage's kernels; a counter summary in profiles/ applies only
-# while these hash to the digest recorded in it.
+# Sources of each stage's kernels (window 256 has kernels of its own); a
+# counter summary in profiles/ applies only while these hash to the digest
+# recorded in it.
 KERNEL_SOURCES = {
-    "fused": ["fused.hip", "mfma256.hip", "decode_common.h", "mfma_common.h", "fptc_internal.h"],
-    "decode": ["decode.hip", "decode_common.h", "mfma_common.h", "fptc_internal.h"],
-    "dequant_idct": ["dqidct_mfma.hip", "dqidct.hip", "mfma256.hip", "mfma_common.h", "fptc_internal.h"],
-    "plan": ["plan.hip", "fptc_internal.h"],
-    "backward": ["bwd.hip", "fptc_internal.h"],
+    ("fused", False): ["fused.hip", "decode_common.h", "mfma_common.h", "fptc_internal.h"],
+    ("fused", True): ["mfma256.hip", "decode_common.h", "mfma_common.h", "fptc_internal.h"],
+    ("decode", False): ["decode.hip", "decode_common.h", "mfma_common.h", "fptc_internal.h"],
+    ("dequant_idct", False): ["dqidct_mfma.hip", "dqidct.hip", "mfma_common.h", "fptc_internal.h"],
+    ("dequant_idct", True): ["mfma256.hip", "dqidct.hip", "mfma_common.h", "fptc_internal.h"],
+    ("plan", False): ["plan.hip", "fptc_internal.h"],
+    ("backward", False): ["bwd.hip", "fptc_internal.h"],
 }
 
 
-def source_digest(stage: str) -> str:
+def source_digest(stage: str, wide: bool = False) -> str:
     import hashlib
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES[stage]:
+    files = KERNEL_SOURCES.get((stage, wide)) or KERNEL_SOURCES[(stage, False)]
+    for f in files:
         with open(os.path.join(ROOT, "paper_2605_01086_amd", "csrc", f), "rb") as fh:
             h.update(f.encode() + b"\0" + fh.read())
     return h.hexdigest()
@@ -263,10 +267,11 @@ def roofline(s: Setup, stage: str, ms: float, precision: str, tag: str) -> dict:
     r = {"bound": "hbm", "kernel": kernel_name(stage, s.q.N, precision), "achieved": round(achieved, 1),
          "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
          "algorithmic_bytes": int(alg), "avg_ms": round(float(ms), 4)}
-    kv, src = read_summary(f"traffic_{tag}", stage)
+    wide = s.q.N == 256
+    kv, src = read_summary(f"traffic_{tag}", stage, wide)
     r["traffic"] = int(float(kv["traffic_bytes_per_dispatch"])) if kv else None
     r["traffic_source"] = src
-    kv, src = read_summary(f"mfma_{tag}", stage)
+    kv, src = read_summary(f"mfma_{tag}", stage, wide)
     if kv and "mfma_util" in kv:
         r["mfma_util"] = float(kv["mfma_util"])
         r["mfma_source"] = src

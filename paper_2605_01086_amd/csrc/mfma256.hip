@@ -38,7 +38,7 @@ namespace {
 constexpr int N256 = 256;
 constexpr int kWaves256 = 8;
 constexpr int kMaxSteps = 8;      // k-steps of 16 bins of one parity (128 bins)
-constexpr int kPre256 = 8;        // rounds of 64 words requested a round ahead (512 words)
+constexpr int kPre256 = 12;       // rounds of 64 words requested a round ahead (768 words)
 constexpr int kSymVec = 8;        // 16-byte symbol vectors per lane requested a round ahead (8 KB)
 // Exchange buffer of a tile: the even waves' sums E[w][n] then the odd waves'
 // O[w][n], 32 windows x 128 columns each, rows padded to 132 floats (so the
