@@ -423,25 +423,38 @@ def release():
     torch.cuda.empty_cache()
 
 
-def leg_fused_vs_fp32(s: Setup, launch, steps, warmup, precisions=("fp16x2",), with_fp32=True):
+def tuned_launch(s: Setup, launch, precision, fused, tune):
+    """The launch shape of one leg: the autotuner's pick on this workload when
+    tune is set, else `launch`; with a record of which."""
+    if not tune:
+        return launch, {"picked_by": "default"}
+    from paper_2605_01086_amd import autotune
+    lt, info = autotune.tune(s.batch, s.codec, precision, fused)
+    return lt, {"shape": info["shape"], "picked_by": "autotuner", "tuning_s": round(info["tuning_s"], 2),
+                "cached": info["cached"]}
+
+
+def leg_fused_vs_fp32(s: Setup, launch, steps, warmup, precisions=("fp16x2",), with_fp32=True, tune=False):
     """Decoded GB/s of the fused path per MFMA precision and of the split FP32
     SIMT path, each with its dominant kernel's roofline fraction; outputs kept
     on the host for the error report."""
     res, outs = {}, {}
     for prec in precisions:
-        dec, ms, modes, per, _ = batched(s, launch, prec, True, steps, warmup)
+        lp, how = tuned_launch(s, launch, prec, True, tune)
+        dec, ms, modes, per, _ = batched(s, lp, prec, True, steps, warmup)
         res[f"fused_{prec}"] = {"value": round(4 * s.n_samples / (ms * 1e-3) / 1e9, 2), "ms_per_step": round(ms, 4),
-                                **modes,
+                                **modes, "launch": how,
                                 "stage_ms": {k: round(v, 4) for k, v in per.items()},
                                 "roofline": roofline(s, "fused", per["fused"], prec, f"fused_{prec}_{s.name}")}
         outs[f"fused_{prec}"] = dec.out[:s.n_samples].cpu().numpy()
         del dec
         release()
     if with_fp32:
-        dec, ms, modes, per, _ = batched(s, launch, "fp32", False, steps, warmup)
+        lp, how = tuned_launch(s, launch, "fp32", False, tune)
+        dec, ms, modes, per, _ = batched(s, lp, "fp32", False, steps, warmup)
         dom = max(per, key=per.get)
         res["split_fp32"] = {"value": round(4 * s.n_samples / (ms * 1e-3) / 1e9, 2), "ms_per_step": round(ms, 4),
-                             **modes,
+                             **modes, "launch": how,
                              "stage_ms": {k: round(v, 4) for k, v in per.items()},
                              "roofline": roofline(s, dom, per[dom], "fp32", f"{dom}_fp32_{s.name}")}
         if dom == "dequant_idct":  # the FP32 SIMT contraction: E fused multiply-adds per sample
@@ -454,13 +467,13 @@ def leg_fused_vs_fp32(s: Setup, launch, steps, warmup, precisions=("fp16x2",), w
     return res, outs
 
 
-def leg_grad(s: Setup, launch, steps, warmup):
+def leg_grad(s: Setup, launch, steps, warmup, tune=False):
     """Forward (plan + fused FP16X2, and the split path the backward needs) and
     backward (coefficient + scale gradients) on the grad workload."""
     import torch
     from paper_2605_01086_amd import codec as C
     from paper_2605_01086_amd import fptc as F
-    res, outs = leg_fused_vs_fp32(s, launch, steps, warmup, ("fp16x2",), True)
+    res, outs = leg_fused_vs_fp32(s, launch, steps, warmup, ("fp16x2",), True, tune)
     dec = C.Decoder(s.batch, s.codec, launch)
     dec.plan()
     dec.decode()
@@ -687,7 +700,7 @@ def main():
                     q = Cc.quant_params("amp", N, N, step_fine=STEP_F, step_coarse=STEP_C, threshold=THRESH)
                     cs = Setup("precision", threads, q)
                     res, outs = leg_fused_vs_fp32(cs, C.Launch(), max(5, args.steps // 2), 2,
-                                                  ("fp16x2", "bf16x3", "fp16", "bf16"), True)
+                                                  ("fp16x2", "bf16x3", "fp16", "bf16"), True, args.autotune)
                     if not args.no_cpu_baseline:
                         res["oracle_error"] = errors_vs_oracle(cs, outs, [0, 1], threads)
                         res["oracle_error"]["streams"] = "streams 0 (EEG-like) and 1 (seismic-like)"
@@ -698,14 +711,14 @@ def main():
                     release()
             elif name == "grad":
                 cs = Setup("grad", threads)
-                entry, outs = leg_grad(cs, C.Launch(), max(5, args.steps // 2), 2)
+                entry, outs = leg_grad(cs, C.Launch(), max(5, args.steps // 2), 2, args.autotune)
                 entry["samples"] = cs.n_samples
                 del outs, cs
                 release()
             elif name in ("plain", "large", "paper"):
                 cs = Setup(name, threads)
                 prec = ("fp16x2",)
-                entry, outs = leg_fused_vs_fp32(cs, C.Launch(), max(5, args.steps // 2), 2, prec, True)
+                entry, outs = leg_fused_vs_fp32(cs, C.Launch(), max(5, args.steps // 2), 2, prec, True, args.autotune)
                 if not args.no_cpu_baseline:
                     if name == "plain":
                         entry["cpu_baseline_single_thread"] = cpu_oracle(cs, [0], 1)
