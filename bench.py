@@ -507,11 +507,12 @@ def leg_grad(s: Setup, launch, steps, warmup, tune=False):
     return res, outs
 
 
-def sweep(threads, steps, warmup):
+def sweep(threads, steps, warmup, tune=True):
     """Decoded GB/s over window N and kept coefficients E at the paper
     quantizer (zones [0, 2) mu-law, [2, E) deadzone), on 128 EEG-like streams
     of 2^20 samples: the fused FP16X2 path (N >= 32) and the split FP32 SIMT
-    path, each step timed in its faster launch mode."""
+    path, each point in the autotuner's launch shape for it (tune) and each
+    step timed in its faster launch mode."""
     from paper_2605_01086_amd import codec as C
     from synth import workloads as W
     w = W.workload("sweep")
@@ -524,12 +525,16 @@ def sweep(threads, steps, warmup):
             s = Setup("sweep", threads, q)
             row = {"N": N, "E": E, "bytes_per_sample_in": round(s.comp_bytes / s.n_samples, 4)}
             if N >= 32:
-                dec, ms, _, per, _ = batched(s, C.Launch(), "fp16x2", True, steps, warmup)
+                lf, how = tuned_launch(s, C.Launch(), "fp16x2", True, tune)
+                row["fused_launch"] = how.get("shape")
+                dec, ms, _, per, _ = batched(s, lf, "fp16x2", True, steps, warmup)
                 row["fused_fp16x2_GBs"] = round(4 * s.n_samples / (ms * 1e-3) / 1e9, 1)
                 row["fused_ms"] = round(ms, 4)
                 row["fused_kernel_frac_hbm"] = roofline(s, "fused", per["fused"], "fp16x2", "sweep")["frac"]
                 del dec
-            dec, ms, _, per, _ = batched(s, C.Launch(), "fp32", False, steps, warmup)
+            ls, how = tuned_launch(s, C.Launch(), "fp32", False, tune)
+            row["split_launch"] = how.get("shape")
+            dec, ms, _, per, _ = batched(s, ls, "fp32", False, steps, warmup)
             row["split_fp32_GBs"] = round(4 * s.n_samples / (ms * 1e-3) / 1e9, 1)
             row["split_ms"] = round(ms, 4)
             row["split_stage_ms"] = {k: round(v, 4) for k, v in per.items()}
@@ -588,7 +593,7 @@ def main():
     from paper_2605_01086_amd import codec as C
     threads = host_threads()
     if args.sweep:
-        rows = sweep(threads, args.steps, args.warmup)
+        rows = sweep(threads, args.steps, args.warmup, args.autotune)
         print(json.dumps({"sweep": rows, "workload": "128 EEG-like streams x 2^20 samples, paper quantizer",
                           "steps": args.steps}), flush=True)
         return
