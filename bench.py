@@ -416,6 +416,29 @@ def errors_vs_oracle(s: Setup, outs: dict, streams, threads):
 # ------------------------------------------------------------------ legs
 
 
+def copy_bandwidth(n_bytes: int = 1 << 30, reps: int = 10) -> dict:
+    """Measured HBM bandwidth of a plain device copy (torch copy_ of n_bytes,
+    read + write), best of reps by HIP events: the practical ceiling beside
+    the 8 TB/s specification."""
+    import torch
+    src = torch.ones(n_bytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    best = float("inf")
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        torch.cuda.synchronize()
+        best = min(best, e0.elapsed_time(e1))
+    del src, dst
+    return {"kernel": "torch copy_ of 1 GiB float32 (read + write)", "GBs": round(2 * n_bytes / (best * 1e-3) / 1e9, 1),
+            "best_ms": round(best, 4)}
+
+
 def release():
     """Return freed device memory to the driver between workloads."""
     import torch
@@ -641,6 +664,10 @@ def main():
                             "max": round(float(gpu.max()), 4)},
         "autotune": tuned,
     }
+    cb = copy_bandwidth()
+    line["copy_bandwidth"] = {**cb, "kernel_frac_of_copy": round(roof["achieved"] / cb["GBs"], 4),
+                              "path_frac_of_copy": round(4 * s.n_samples / (ms_step * 1e-3) / 1e9 / cb["GBs"]
+                                                         * (4 + s.comp_bytes / s.n_samples) / 4, 4)}
     head_host = head_out.cpu().numpy()
     out32_host = None
     if args.workload == "batch":
