@@ -418,8 +418,8 @@ def errors_vs_oracle(s: Setup, outs: dict, streams, threads):
 
 def copy_bandwidth(n_bytes: int = 1 << 30, reps: int = 10) -> dict:
     """Measured HBM bandwidth of a plain device copy (torch copy_ of n_bytes,
-    read + write), best of reps by HIP events: the practical ceiling beside
-    the 8 TB/s specification."""
+    read + write) and of a fill (write only), best of reps by HIP events: the
+    practical ceilings beside the 8 TB/s specification."""
     import torch
     src = torch.ones(n_bytes // 4, dtype=torch.float32, device="cuda")
     dst = torch.empty_like(src)
@@ -434,9 +434,17 @@ def copy_bandwidth(n_bytes: int = 1 << 30, reps: int = 10) -> dict:
         e1.record()
         torch.cuda.synchronize()
         best = min(best, e0.elapsed_time(e1))
+    fbest = float("inf")  # write only: the output side of a decode
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        dst.fill_(1.0)
+        e1.record()
+        torch.cuda.synchronize()
+        fbest = min(fbest, e0.elapsed_time(e1))
     del src, dst
     return {"kernel": "torch copy_ of 1 GiB float32 (read + write)", "GBs": round(2 * n_bytes / (best * 1e-3) / 1e9, 1),
-            "best_ms": round(best, 4)}
+            "best_ms": round(best, 4), "fill_GBs": round(n_bytes / (fbest * 1e-3) / 1e9, 1)}
 
 
 def release():
