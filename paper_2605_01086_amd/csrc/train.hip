@@ -79,7 +79,7 @@ __global__ void __launch_bounds__(kThreads) k_fdct_quant(int n_streams, const in
   const int64_t n_win = sym_off[n_streams] / E;
   for (int64_t g0 = (int64_t)blockIdx.x * G; g0 < n_win; g0 += (int64_t)gridDim.x * G) {
     __syncthreads();  // the previous group's reads are done
-    if (threadIdx.x < G) {
+    if ((int)threadIdx.x < G) {
       const int64_t g = g0 + threadIdx.x;
       int64_t base = 0, len = 0, sb = -1;
       if (g < n_win) {
