@@ -125,8 +125,8 @@ def test_autograd_and_adam_refit(precision):
     np.testing.assert_allclose(gamma.cpu().numpy(), og, atol=2e-3)
 
 
-@pytest.mark.parametrize("N,E", [(128, 128), (32, 16)])
-def test_autograd_coefficient_input(N, E):
+@pytest.mark.parametrize("N,E,precision", [(128, 128, "fp32"), (32, 16, "fp32"), (64, 64, "fp16x2")])
+def test_autograd_coefficient_input(N, E, precision):
     """The autograd Function's additive coefficient input: its gradient is the
     oracle's coefficient gradient of the MSE, and its forward term is the
     oracle's per-window inverse DCT of the coefficients."""
@@ -140,7 +140,7 @@ def test_autograd_coefficient_input(N, E):
     n_sym = dec.batch.n_symbols
     g = torch.ones((len(c.signals), 3), dtype=torch.float64, device="cuda")
     delta = torch.zeros(n_sym, dtype=torch.float32, device="cuda", requires_grad=True)
-    loss = R.mse(R.DequantIDCT.apply(g, dec, "fp32", delta), x)
+    loss = R.mse(R.DequantIDCT.apply(g, dec, precision, delta), x)
     loss.backward()
     got = delta.grad.cpu().numpy()
     M = x.numel()
@@ -155,8 +155,8 @@ def test_autograd_coefficient_input(N, E):
     dv = rng.standard_normal(n_sym).astype(np.float32)
     with torch.no_grad():
         dvt = torch.from_numpy(dv).cuda()
-        a = R.DequantIDCT.apply(g, dec, "fp32", dvt).cpu().numpy()
-        b = R.DequantIDCT.apply(g, dec, "fp32").cpu().numpy()
+        a = R.DequantIDCT.apply(g, dec, precision, dvt).cpu().numpy()
+        b = R.DequantIDCT.apply(g, dec, precision).cpu().numpy()
         term = R.idct_coefficients(dec, dvt).cpu().numpy()
     # the forward adds the term (one float32 rounding of the sum)
     assert np.all(np.abs(a - (b + term)) <= 2 * np.finfo(np.float32).eps * np.maximum(np.abs(a), 1.0))

@@ -39,7 +39,7 @@ def test_fused_launch_shapes(wpc, waves, blocks):
     check_parity(c, f, tol=1e-5, check_symbols=False)
 
 
-@pytest.mark.parametrize("N,E", [(32, 16), (64, 20), (128, 100), (256, 180)])
+@pytest.mark.parametrize("N,E", [(32, 16), (64, 20), (64, 64), (128, 100), (256, 180), (256, 256)])
 def test_fused_paper_quantizer_with_scales(N, E):
     p = paper_params(N, E, "eeg", 1600 + N)
     c = build_case(p, ["eeg", "seismic"], [N * 150 + 7, 3001, 5, N * 31], config_id=1600 + N, gamma=True)
