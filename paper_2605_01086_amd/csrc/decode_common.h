@@ -366,7 +366,7 @@ __device__ inline int decode_word_sparse(uint64_t wd, unsigned char *p, int cnt,
   unsigned char *const pe = p + cnt;
   int bits = 0, fl = 0;
   uint32_t e = 0;
-  while (pe - p >= 16) {
+  while ((int)(pe - p) >= 16) {
     e = L[(uint32_t)(wd >> 32) >> hs];
     const int len = (e >> 12) & 15;
     wd <<= len;
